@@ -1,0 +1,151 @@
+"""Benchmark of the sparsity-path SMC hot path on one MI355X.
+
+One "step" is one pass of the whole hot path at one prior scale: prior-ratio reweight,
+logsumexp/ESS, (systematic resampling), S move sweeps (proposal -> MFMA log-likelihood
+contraction (+ adjoint for MALA) -> MH decisions) and weighted moments, over the N
+particles of the workload.  The workload is the n=5000 / p=200 / N=16384 MALA run with
+BF16 hi+lo contractions (LD blocks of 20, a = 1, 100 scales, 10 sweeps per scale).
+
+    python bench.py [--steps K] [--warmup W] [--workload cfg3] [--no-cpu]
+
+Prints one JSON line.  `value` is whole-job algorithmic contraction throughput
+(2 N n p flops per log-likelihood evaluation plus 2 N n p per gradient evaluation)
+over the K timed steps, inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"bf16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}     # dense MFMA TFLOP/s of MI355X
+HBM_PEAK_GBS = 8000.0
+
+
+def gemm_flops(cfg) -> float:
+    """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
+    f = 2.0 * cfg.N * cfg.n * cfg.p
+    return f * (2.0 if cfg.move == "mala" else 1.0)
+
+
+def cpu_baseline(cfg, X, y, budget_s: float = 15.0):
+    """The oracle (FP64 NumPy, untuned) on a bounded sample: whole MALA/RW sweeps of a
+    subset of the particles, timed on the host's cores."""
+    from oracle import likelihood, smc
+
+    Xs, _, _ = likelihood.standardise(X)
+    prob = smc.Problem(Xs=Xs, y=y.astype(np.float64), a=cfg.a)
+    M = 1024
+    rng = np.random.default_rng(0)
+    beta = rng.normal(0, 0.05, size=(M, cfg.p))
+    if cfg.move == "mala":
+        ll, gl = prob.loglik_and_grad(beta)
+    else:
+        ll, gl = prob.loglik(beta), np.zeros_like(beta)
+    st = smc.State(beta=beta, ll=ll, gl=gl, logW=np.full(M, -math.log(M)))
+    sweep = smc.mala_sweep if cfg.move == "mala" else smc.rwm_sweep
+    sigma = np.full(cfg.p, 0.02)
+    t0 = time.perf_counter()
+    sweeps = 0
+    while True:
+        sweep(prob, st, 1.0, 0.3, sigma, 0, sweeps, 1)
+        sweeps += 1
+        if time.perf_counter() - t0 >= budget_s or sweeps >= 200:
+            break
+    el = time.perf_counter() - t0
+    flops = gemm_flops(cfg) * M / cfg.N * sweeps
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count()
+    return {"value": flops / el / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sweeps} {cfg.move.upper()} sweeps of {M} of the {cfg.N} particles "
+                      f"(n={cfg.n}, p={cfg.p}), FP64 NumPy, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--init-sweeps", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler "
+              "shards particles across GPUs only by design, not in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    from synth import CONFIGS, make_dataset
+
+    cfg = CONFIGS[args.workload]
+    if args.steps + args.warmup > cfg.T - 1:
+        sys.exit(f"steps + warmup must be <= {cfg.T - 1} scales")
+    d = make_dataset(cfg)
+    torch.cuda.set_device(0)
+    over = {}
+    if args.init_sweeps is not None:
+        over["init_sweeps"] = args.init_sweeps
+    s = SpaSMC(SamplerConfig.from_workload(cfg, **over), d.X, d.y)
+    for _ in range(args.warmup):
+        s.step()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [s.step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    tim = s.timing()
+    ms_step = el * 1e3 / args.steps
+    flops_step = gemm_flops(cfg) * cfg.sweeps
+    value = flops_step / (ms_step * 1e-3) / 1e12
+    gemm_ms, gemm_n = tim["loglik"]
+    gemm_avg_ms = gemm_ms / max(gemm_n, 1)
+    achieved = gemm_flops(cfg) / (gemm_avg_ms * 1e-3) / 1e12
+    dtype = {"bf16x2": "bf16", "fp32": "f32", "fp64": "f64"}[cfg.prec]
+    peak = PEAK[cfg.prec]
+    out = {
+        "metric": "loglik TFLOP/s + SPA sweep ESS/sec: plain FP32 RWM vs mixed-prec MALA",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: n={cfg.n} p={cfg.p} N={cfg.N} a={cfg.a} "
+                               f"{cfg.move.upper()} S={cfg.sweeps} {cfg.prec}"
+                               + (f"/{cfg.xfmt}" if cfg.prec == "bf16x2" else ""),
+                   "n": cfg.n, "p": cfg.p, "N": cfg.N, "sweeps_per_step": cfg.sweeps,
+                   "move": cfg.move, "prec": cfg.prec},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "loglik_kernel (fused log-likelihood + adjoint)" if cfg.move == "mala"
+                     else "loglik_kernel", "avg_launch_us": round(gemm_avg_ms * 1e3, 2)},
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
+        "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, d.X, d.y)
+    s.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,813 @@
+// C-ABI implementation: handle, validation, buffers and the per-scale orchestration of the
+// sampler (Section 4): reweight -> normalise/ESS -> [resample] -> sweeps -> moments.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/spa_smc.h"
+#include "spa_internal.hpp"
+#include "spa_kernels.hpp"
+
+using namespace spa;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+constexpr int kMaxPP = 512;
+constexpr double kSigmaFloor = 1e-12;
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+int ceil_log2(long long m) {
+  int k = 0;
+  while ((1LL << k) < m) ++k;
+  return k;
+}
+
+// Host copy of Philox4x32-10 for the resampling offsets (same definition as the device one).
+uint32_t philox_w0(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = 0xD2511F53ull * c0, p1 = 0xCD9E8D57ull * c2;
+    const uint32_t hi0 = static_cast<uint32_t>(p0 >> 32), lo0 = static_cast<uint32_t>(p0);
+    const uint32_t hi1 = static_cast<uint32_t>(p1 >> 32), lo1 = static_cast<uint32_t>(p1);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return c0;
+}
+
+struct XPack {
+  void *Xk = nullptr, *Xt = nullptr, *yv = nullptr;
+  int PP = 0;
+  bool fp8 = false;
+  bool ready = false;
+};
+
+struct OpScratch {
+  void *Bhi = nullptr, *Blo = nullptr;
+  double *moff = nullptr, *yb = nullptr;
+  size_t cap = 0;   // rows
+  int PP = 0;
+};
+
+}  // namespace
+
+struct spa_smc {
+  // configuration
+  int n = 0, p = 0, N = 0, T = 0;
+  double a = 1.0;
+  int a_inf = 0;
+  spa_move move = SPA_MOVE_RWM;
+  int sweeps = 0, init_sweeps = 0, adapt = 1;
+  double ess_frac = 0.5, step = 1.0;
+  Prec prec = Prec::F64;
+  spa_xfmt xfmt = SPA_X_AUTO;
+  uint32_t k0 = 0, k1 = 0;
+  std::vector<double> lambda;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int n_pad = 0, Npad = 0, PP = 0;
+  bool f64 = true;
+  size_t psz = 8;
+  // device data
+  uint8_t *dX = nullptr, *dy = nullptr;
+  double *mu = nullptr, *s = nullptr, *inv_s = nullptr, *ytil = nullptr;
+  int *dbad = nullptr;
+  XPack xp[3];
+  void *beta = nullptr, *prop = nullptr, *tmp = nullptr;
+  void *gl = nullptr, *glp = nullptr, *gltmp = nullptr;
+  double *ll = nullptr, *llp = nullptr, *lltmp = nullptr, *logw = nullptr;
+  double *lpc = nullptr, *lpp = nullptr, *lqf = nullptr;
+  int *acc = nullptr, *anc = nullptr;
+  OpScratch op;                  // operand of the sampler's own sweeps
+  double *sigma = nullptr, *mean_path = nullptr, *var_path = nullptr, *part = nullptr;
+  double *cdf = nullptr, *scal = nullptr;
+  size_t cdf_cap = 0;
+  long long *dcount = nullptr;
+  double *hscal = nullptr;       // pinned host
+  long long *hcount = nullptr;   // pinned host
+  OpScratch scr[3];              // operands of loglik/grad calls, per precision
+  void *gscr = nullptr;
+  size_t gscr_cap = 0;
+  double *llscr = nullptr;
+  size_t llscr_cap = 0;
+  std::vector<void *> allocs;
+  // optional per-kernel-class timing with HIP events on the handle's stream
+  bool timing = false;
+  std::vector<hipEvent_t> ev;      // pool, used in (start, stop) pairs
+  std::vector<int> ev_cat;         // category of each recorded pair
+  double t_ms[SPA_TIMING_CLASSES] = {0};
+  long long t_cnt[SPA_TIMING_CLASSES] = {0};
+  // path
+  int t = 0;
+  double log_z = 0.0;
+  std::vector<spa_smc_stats> stats;
+  std::vector<double> logz_path;
+  std::string err;
+};
+
+namespace {
+
+spa_status set_err(spa_smc *h, spa_status st, const std::string &msg) {
+  if (h) h->err = msg;
+  else g_init_error = msg;
+  return st;
+}
+
+spa_status hip_fail(spa_smc *h, hipError_t e, const char *what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return set_err(h, SPA_ERR_HIP, m);
+}
+
+#define SPA_CK(h, expr)                                   \
+  do {                                                    \
+    hipError_t e_ = (expr);                               \
+    if (e_ != hipSuccess) return hip_fail((h), e_, #expr); \
+  } while (0)
+
+template <typename P>
+spa_status dalloc(spa_smc *h, P **ptr, size_t bytes) {
+  void *v = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&v, bytes);
+  if (e != hipSuccess) return set_err(h, SPA_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e));
+  h->allocs.push_back(v);
+  e = hipMemsetAsync(v, 0, bytes, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemsetAsync");
+  *ptr = static_cast<P *>(v);
+  return SPA_OK;
+}
+
+void dfree(spa_smc *h, void *v) {
+  if (!v) return;
+  for (auto it = h->allocs.begin(); it != h->allocs.end(); ++it)
+    if (*it == v) {
+      h->allocs.erase(it);
+      break;
+    }
+  (void)hipFree(v);
+}
+
+Prec to_prec(spa_prec p) {
+  return p == SPA_PREC_FP64 ? Prec::F64 : (p == SPA_PREC_FP32 ? Prec::F32 : Prec::BF16X2);
+}
+
+Prior make_prior(const spa_smc *h, double lam) {
+  Prior pr;
+  pr.a = h->a;
+  pr.lam = lam;
+  pr.inf = h->a_inf;
+  pr.log2lam = std::log(2.0 * lam);
+  return pr;
+}
+
+// ---- timing: tbeg/tend bracket one launch; flush after a synchronisation point
+void tbeg(spa_smc *h, int cat) {
+  if (!h->timing) return;
+  const size_t k = 2 * h->ev_cat.size();
+  while (h->ev.size() < k + 2) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) {
+      h->timing = false;
+      return;
+    }
+    h->ev.push_back(e);
+  }
+  h->ev_cat.push_back(cat);
+  (void)hipEventRecord(h->ev[k], h->stream);
+}
+void tend(spa_smc *h) {
+  if (!h->timing || h->ev_cat.empty()) return;
+  (void)hipEventRecord(h->ev[2 * h->ev_cat.size() - 1], h->stream);
+}
+void tflush(spa_smc *h) {   // the stream must be synchronised
+  for (size_t i = 0; i < h->ev_cat.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+      h->t_ms[h->ev_cat[i]] += ms;
+      h->t_cnt[h->ev_cat[i]] += 1;
+    }
+  }
+  h->ev_cat.clear();
+}
+
+size_t bt_size(Prec p) { return p == Prec::F64 ? 8 : (p == Prec::F32 ? 4 : 2); }
+
+spa_status ensure_xpack(spa_smc *h, Prec prec) {
+  XPack &x = h->xp[static_cast<int>(prec)];
+  if (x.ready) return SPA_OK;
+  const int PP = gemm_pad_markers(h->p, prec);
+  if (PP < 0) return set_err(h, SPA_ERR_ARG, "p too large for this precision");
+  x.PP = PP;
+  x.fp8 = (prec == Prec::BF16X2) && (h->xfmt == SPA_X_FP8E4M3);
+  XFormat f = prec == Prec::F64 ? XFormat::F64
+              : prec == Prec::F32 ? XFormat::F32
+              : (x.fp8 ? XFormat::FP8 : XFormat::BF16);
+  const size_t es = prec == Prec::F64 ? 8 : prec == Prec::F32 ? 4 : (x.fp8 ? 1 : 2);
+  spa_status st;
+  if ((st = dalloc(h, &x.Xk, es * (size_t)h->n_pad * PP)) != SPA_OK) return st;
+  if ((st = dalloc(h, &x.Xt, es * (size_t)h->n_pad * PP)) != SPA_OK) return st;
+  const bool yf64 = prec == Prec::F64;
+  if ((st = dalloc(h, &x.yv, (yf64 ? 8 : 4) * (size_t)h->n_pad)) != SPA_OK) return st;
+  launch_pack_x(f, h->dX, h->n, h->p, h->n_pad, PP, x.Xk, x.Xt, h->stream);
+  launch_labels(h->dy, h->n, h->n_pad, yf64, x.yv, h->stream);
+  SPA_CK(h, hipGetLastError());
+  x.ready = true;
+  return SPA_OK;
+}
+
+spa_status ensure_op(spa_smc *h, OpScratch &o, Prec prec, int PP, size_t rows) {
+  if (o.cap >= rows && o.PP == PP) return SPA_OK;
+  dfree(h, o.Bhi);
+  dfree(h, o.Blo);
+  dfree(h, o.moff);
+  dfree(h, o.yb);
+  o = OpScratch{};
+  spa_status st;
+  const size_t bs = bt_size(prec);
+  if ((st = dalloc(h, &o.Bhi, bs * rows * PP)) != SPA_OK) return st;
+  if ((st = dalloc(h, &o.Blo, prec == Prec::BF16X2 ? bs * rows * PP : 16)) != SPA_OK) return st;
+  if ((st = dalloc(h, &o.moff, 8 * rows)) != SPA_OK) return st;
+  if ((st = dalloc(h, &o.yb, 8 * rows)) != SPA_OK) return st;
+  o.cap = rows;
+  o.PP = PP;
+  return SPA_OK;
+}
+
+GemmArgs gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g) {
+  const XPack &x = h->xp[static_cast<int>(prec)];
+  GemmArgs a;
+  a.prec = prec;
+  a.PP = x.PP;
+  a.grad = grad;
+  a.x_fp8 = x.fp8;
+  a.Xk = x.Xk;
+  a.Xt = x.Xt;
+  a.yv = x.yv;
+  a.Bhi = o.Bhi;
+  a.Blo = o.Blo;
+  a.moff = o.moff;
+  a.yb = o.yb;
+  a.mu = h->mu;
+  a.inv_s = h->inv_s;
+  a.n = h->n;
+  a.n_pad = h->n_pad;
+  a.M = M;
+  a.p = h->p;
+  a.ll = ll;
+  a.g = g;
+  return a;
+}
+
+// Log-likelihood (and gradient) of the handle's own particle buffer `beta` into ll/g.
+spa_status eval_state(spa_smc *h, const void *beta, double *ll, void *g) {
+  launch_pack_b(h->prec, h->f64, beta, h->N, h->Npad, h->p, h->PP, h->mu, h->s, h->inv_s, h->ytil,
+                h->op.Bhi, h->op.Blo, h->op.moff, h->op.yb, h->stream);
+  const bool grad = h->move == SPA_MOVE_MALA;
+  SPA_CK(h, launch_loglik(gemm_args(h, h->prec, h->op, h->N, grad, ll, grad ? g : nullptr), h->stream));
+  return SPA_OK;
+}
+
+// One sweep targeting pi(. | lam): propose -> contraction (+ adjoint) -> MH decision.
+spa_status sweep(spa_smc *h, int t, int s, double lam) {
+  const bool mala = h->move == SPA_MOVE_MALA;
+  const Prior pr = make_prior(h, lam);
+  ProposeArgs pa{};
+  pa.beta = h->beta;
+  pa.gl = h->gl;
+  pa.prop = h->prop;
+  pa.Bhi = h->op.Bhi;
+  pa.Blo = h->op.Blo;
+  pa.moff = h->op.moff;
+  pa.yb = h->op.yb;
+  pa.lp_cur = h->lpc;
+  pa.lp_prop = h->lpp;
+  pa.lqf = h->lqf;
+  pa.sigma = h->sigma;
+  pa.cc.mu = h->mu;
+  pa.cc.s = h->s;
+  pa.cc.inv_s = h->inv_s;
+  pa.cc.ytil = h->ytil;
+  pa.prior = pr;
+  pa.step = h->step;
+  pa.sqrt_step = std::sqrt(h->step);
+  pa.M = h->N;
+  pa.M_pad = h->Npad;
+  pa.p = h->p;
+  pa.PP = h->PP;
+  pa.k0 = h->k0;
+  pa.k1 = h->k1;
+  pa.sweep = static_cast<uint32_t>(s);
+  pa.t = t;
+  tbeg(h, SPA_T_PROPOSE);
+  launch_propose(h->prec, mala, pa, h->stream);
+  tend(h);
+  tbeg(h, SPA_T_LOGLIK);
+  SPA_CK(h, launch_loglik(gemm_args(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr),
+                          h->stream));
+  tend(h);
+  AcceptArgs aa{};
+  aa.beta = h->beta;
+  aa.gl = h->gl;
+  aa.prop = h->prop;
+  aa.gl_prop = h->glp;
+  aa.ll = h->ll;
+  aa.ll_prop = h->llp;
+  aa.lp_cur = h->lpc;
+  aa.lp_prop = h->lpp;
+  aa.lqf = h->lqf;
+  aa.sigma = h->sigma;
+  aa.acc_cnt = h->acc;
+  aa.prior = pr;
+  aa.step = h->step;
+  aa.M = h->N;
+  aa.p = h->p;
+  aa.k0 = h->k0;
+  aa.k1 = h->k1;
+  aa.sweep = static_cast<uint32_t>(s);
+  aa.t = t;
+  tbeg(h, SPA_T_ACCEPT);
+  launch_accept(h->f64, mala, aa, h->stream);
+  tend(h);
+  SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+spa_status read_count(spa_smc *h, long long *out) {
+  launch_count(h->acc, h->N, h->dcount, h->stream);
+  SPA_CK(h, hipMemcpyAsync(h->hcount, h->dcount, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  *out = h->hcount[0];
+  return SPA_OK;
+}
+
+void adapt_step(spa_smc *h, double acc_rate) {
+  if (!h->adapt) return;
+  const double target = h->move == SPA_MOVE_MALA ? 0.574 : 0.234;
+  double d = acc_rate - target;
+  const double l2 = std::log(2.0);
+  d = std::min(std::max(d, -l2), l2);
+  h->step *= std::exp(d);
+}
+
+spa_status record_moments(spa_smc *h, int row) {
+  tbeg(h, SPA_T_MOMENTS);
+  launch_moments(h->f64, h->beta, h->logw, h->N, h->p, h->part, h->mean_path + (size_t)row * h->p,
+                 h->var_path + (size_t)row * h->p, nullptr, kSigmaFloor, h->stream);
+  tend(h);
+  SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+spa_status validate_cfg(const spa_smc_config *c) {
+  if (!c) return set_err(nullptr, SPA_ERR_ARG, "cfg is NULL");
+  if (c->n < 1 || c->p < 1 || c->N < 1) return set_err(nullptr, SPA_ERR_SHAPE, "n, p and N must be >= 1");
+  if (c->p > kMaxPP - 1) return set_err(nullptr, SPA_ERR_SHAPE, "p must be <= 511");
+  if ((long long)c->n * c->p > (1LL << 31) || (long long)c->N * c->p > (1LL << 31))
+    return set_err(nullptr, SPA_ERR_SHAPE, "problem too large for 32-bit indices");
+  if (!(c->a > 0.0)) return set_err(nullptr, SPA_ERR_ARG, "a must be > 0");
+  if (c->T < 1 || !c->lambda) return set_err(nullptr, SPA_ERR_ARG, "T >= 1 and lambda required");
+  for (int i = 0; i < c->T; ++i) {
+    if (!(c->lambda[i] > 0.0) || !std::isfinite(c->lambda[i]))
+      return set_err(nullptr, SPA_ERR_ARG, "lambda must be finite and > 0");
+    if (i && !(c->lambda[i] < c->lambda[i - 1]))
+      return set_err(nullptr, SPA_ERR_ARG, "lambda must be strictly decreasing");
+  }
+  if (c->move != SPA_MOVE_RWM && c->move != SPA_MOVE_MALA) return set_err(nullptr, SPA_ERR_ARG, "bad move");
+  if (c->sweeps < 0 || c->init_sweeps < 0) return set_err(nullptr, SPA_ERR_ARG, "sweeps must be >= 0");
+  if (!(c->ess_frac > 0.0 && c->ess_frac <= 1.0)) return set_err(nullptr, SPA_ERR_ARG, "ess_frac in (0, 1]");
+  if (!(c->step0 > 0.0) || !std::isfinite(c->step0)) return set_err(nullptr, SPA_ERR_ARG, "step0 must be > 0");
+  if (c->adapt != 0 && c->adapt != 1) return set_err(nullptr, SPA_ERR_ARG, "adapt must be 0 or 1");
+  if (c->prec != SPA_PREC_FP64 && c->prec != SPA_PREC_FP32 && c->prec != SPA_PREC_BF16X2)
+    return set_err(nullptr, SPA_ERR_ARG, "bad prec");
+  if (c->xfmt != SPA_X_AUTO && c->xfmt != SPA_X_FP8E4M3 && c->xfmt != SPA_X_BF16)
+    return set_err(nullptr, SPA_ERR_ARG, "bad xfmt");
+  if (c->prec == SPA_PREC_FP64 && c->p > 255) return set_err(nullptr, SPA_ERR_SHAPE, "FP64 path needs p <= 255");
+  return SPA_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+
+extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_host, const uint8_t *y_host,
+                                   void *hip_stream, spa_smc **out) {
+  g_init_error.clear();
+  if (!out) return set_err(nullptr, SPA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  spa_status st = validate_cfg(cfg);
+  if (st != SPA_OK) return st;
+  if (!X_host || !y_host) return set_err(nullptr, SPA_ERR_ARG, "X and y are required");
+  const int n = cfg->n, p = cfg->p;
+  for (size_t i = 0; i < (size_t)n * p; ++i)
+    if (X_host[i] > 2) return set_err(nullptr, SPA_ERR_ARG, "genotypes must be 0, 1 or 2");
+  for (int k = 0; k < n; ++k)
+    if (y_host[k] > 1) return set_err(nullptr, SPA_ERR_ARG, "labels must be 0 or 1");
+  for (int j = 0; j < p; ++j) {
+    uint8_t lo = 255, hi = 0;
+    for (int k = 0; k < n; ++k) {
+      lo = std::min(lo, X_host[(size_t)k * p + j]);
+      hi = std::max(hi, X_host[(size_t)k * p + j]);
+    }
+    if (lo == hi) return set_err(nullptr, SPA_ERR_SHAPE, "marker " + std::to_string(j) + " has zero variance");
+  }
+
+  spa_smc *h = new (std::nothrow) spa_smc();
+  if (!h) return set_err(nullptr, SPA_ERR_ALLOC, "handle allocation failed");
+  h->n = n;
+  h->p = p;
+  h->N = cfg->N;
+  h->T = cfg->T;
+  h->a = cfg->a;
+  h->a_inf = std::isinf(cfg->a) ? 1 : 0;
+  h->move = cfg->move;
+  h->sweeps = cfg->sweeps;
+  h->init_sweeps = cfg->init_sweeps;
+  h->ess_frac = cfg->ess_frac;
+  h->step = cfg->step0;
+  h->adapt = cfg->adapt;
+  h->prec = to_prec(cfg->prec);
+  h->xfmt = cfg->xfmt;
+  h->k0 = static_cast<uint32_t>(cfg->seed & 0xFFFFFFFFull);
+  h->k1 = static_cast<uint32_t>(cfg->seed >> 32);
+  h->lambda.assign(cfg->lambda, cfg->lambda + cfg->T);
+  h->stream = static_cast<hipStream_t>(hip_stream);
+  h->f64 = h->prec == Prec::F64;
+  h->psz = h->f64 ? 8 : 4;
+  h->n_pad = round_up(n, kIndPad);
+  h->Npad = round_up(h->N, kPartPad);
+  h->PP = gemm_pad_markers(p, h->prec);
+
+  auto fail = [&](spa_status s) {
+    g_init_error = h->err;
+    spa_smc_destroy(h);
+    return s;
+  };
+  hipError_t he = hipGetDevice(&h->device);
+  if (he != hipSuccess) {
+    hip_fail(h, he, "hipGetDevice");
+    return fail(SPA_ERR_HIP);
+  }
+  const size_t NP = (size_t)h->Npad * p;
+  const bool mala = h->move == SPA_MOVE_MALA;
+#define SPA_AL(ptr, bytes) \
+  if ((st = dalloc(h, &(ptr), (bytes))) != SPA_OK) return fail(st)
+  SPA_AL(h->dX, (size_t)n * p);
+  SPA_AL(h->dy, (size_t)n);
+  SPA_AL(h->mu, 8 * kMaxPP);
+  SPA_AL(h->s, 8 * kMaxPP);
+  SPA_AL(h->inv_s, 8 * kMaxPP);
+  SPA_AL(h->ytil, 8 * kMaxPP);
+  SPA_AL(h->dbad, 16);
+  SPA_AL(h->beta, h->psz * NP);
+  SPA_AL(h->prop, h->psz * NP);
+  SPA_AL(h->tmp, h->psz * NP);
+  SPA_AL(h->gl, mala ? h->psz * NP : 16);
+  SPA_AL(h->glp, mala ? h->psz * NP : 16);
+  SPA_AL(h->gltmp, mala ? h->psz * NP : 16);
+  SPA_AL(h->ll, 8 * (size_t)h->Npad);
+  SPA_AL(h->llp, 8 * (size_t)h->Npad);
+  SPA_AL(h->lltmp, 8 * (size_t)h->Npad);
+  SPA_AL(h->logw, 8 * (size_t)h->Npad);
+  SPA_AL(h->lpc, 8 * (size_t)h->Npad);
+  SPA_AL(h->lpp, 8 * (size_t)h->Npad);
+  SPA_AL(h->lqf, 8 * (size_t)h->Npad);
+  SPA_AL(h->acc, 4 * (size_t)h->Npad);
+  SPA_AL(h->anc, 4 * (size_t)h->Npad);
+  SPA_AL(h->sigma, 8 * kMaxPP);
+  SPA_AL(h->mean_path, 8 * (size_t)h->T * p);
+  SPA_AL(h->var_path, 8 * (size_t)h->T * p);
+  SPA_AL(h->part, 8 * 3 * (size_t)moments_chunks(h->N) * p);
+  SPA_AL(h->cdf, 8 * (size_t)h->Npad);
+  h->cdf_cap = h->Npad;
+  SPA_AL(h->scal, 8 * 16);
+  SPA_AL(h->dcount, 16);
+#undef SPA_AL
+  if (hipHostMalloc(reinterpret_cast<void **>(&h->hscal), 16 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&h->hcount), 2 * sizeof(long long)) != hipSuccess) {
+    set_err(h, SPA_ERR_ALLOC, "hipHostMalloc failed");
+    return fail(SPA_ERR_ALLOC);
+  }
+  if ((st = ensure_op(h, h->op, h->prec, h->PP, h->Npad)) != SPA_OK) return fail(st);
+
+  // ---- operand preparation (once)
+  he = hipMemcpyAsync(h->dX, X_host, (size_t)n * p, hipMemcpyHostToDevice, h->stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(h->dy, y_host, (size_t)n, hipMemcpyHostToDevice, h->stream);
+  if (he != hipSuccess) {
+    hip_fail(h, he, "hipMemcpyAsync");
+    return fail(SPA_ERR_HIP);
+  }
+  launch_col_stats(h->dX, h->dy, n, p, h->mu, h->s, h->inv_s, h->ytil, h->dbad, h->stream);
+  if ((st = ensure_xpack(h, h->prec)) != SPA_OK) return fail(st);
+
+  // ---- initial particles: beta = 0, burn-in targeting pi_1, equal weights
+  launch_fill(h->logw, h->N, -std::log(static_cast<double>(h->N)), h->stream);
+  launch_fill(h->sigma, p, 2.0 / std::sqrt(static_cast<double>(n)), h->stream);
+  if ((st = eval_state(h, h->beta, h->ll, h->gl)) != SPA_OK) return fail(st);
+  for (int s = 0; s < h->init_sweeps; ++s) {
+    if (s == h->init_sweeps / 2) {
+      launch_moments(h->f64, h->beta, h->logw, h->N, p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
+                     h->stream);
+    }
+    launch_zero_int(h->acc, h->N, h->stream);
+    if ((st = sweep(h, 0, s, h->lambda[0])) != SPA_OK) return fail(st);
+    long long cnt = 0;
+    if ((st = read_count(h, &cnt)) != SPA_OK) return fail(st);
+    adapt_step(h, static_cast<double>(cnt) / h->N);
+  }
+  if ((st = record_moments(h, 0)) != SPA_OK) return fail(st);
+  he = hipStreamSynchronize(h->stream);
+  if (he != hipSuccess) {
+    hip_fail(h, he, "init");
+    return fail(SPA_ERR_HIP);
+  }
+  h->t = 1;
+  h->log_z = 0.0;
+  spa_smc_stats s0{};
+  s0.t = 1;
+  s0.resampled = 0;
+  s0.lambda = h->lambda[0];
+  s0.ess = h->N;
+  s0.log_z_inc = 0.0;
+  s0.log_z = 0.0;
+  s0.accept_rate = NAN;
+  s0.step = h->step;
+  h->stats.assign(1, s0);
+  h->logz_path.assign(h->T, 0.0);
+  *out = h;
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (h->t < 1) return set_err(h, SPA_ERR_STATE, "handle not initialised");
+  if (h->t >= h->T) return set_err(h, SPA_ERR_STATE, "already at the last scale");
+  const int t_new = h->t + 1;                // 1-based index of the new target
+  const double lam_new = h->lambda[t_new - 1], lam_old = h->lambda[t_new - 2];
+  const bool mala = h->move == SPA_MOVE_MALA;
+  spa_status st;
+
+  // ---- incremental weights, normalisation, ESS, resampling decision (Section 4)
+  tbeg(h, SPA_T_REWEIGHT);
+  launch_reweight(h->f64, h->beta, h->N, h->p, h->a, h->a_inf, lam_new, lam_old, h->logw, h->stream);
+  tend(h);
+  LseArgs la{};
+  la.mode = 0;
+  la.M = h->N;
+  la.K = 53 - ceil_log2(h->N);
+  la.ess_frac = h->ess_frac;
+  la.logw = h->logw;
+  la.cdf = h->cdf;
+  la.anc = h->anc;
+  la.scalars = h->scal;
+  la.u32 = philox_w0(0, 0, 0, (static_cast<uint32_t>(t_new) << 4) | 2u, h->k0, h->k1);
+  tbeg(h, SPA_T_LSE);
+  launch_lse_resample(la, h->stream);
+  tend(h);
+  SPA_CK(h, hipGetLastError());
+  SPA_CK(h, hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  const double ess = h->hscal[0], L = h->hscal[1];
+  const bool resampled = h->hscal[2] != 0.0;
+  if (h->hscal[4] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "non-finite weights");
+  if (resampled) {
+    if (h->hscal[5] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "invalid weights in resampling");
+    tbeg(h, SPA_T_GATHER);
+    launch_gather(h->f64, h->anc, h->N, h->p, h->beta, h->tmp, mala ? h->gl : nullptr, mala ? h->gltmp : nullptr,
+                  h->ll, h->lltmp, h->stream);
+    tend(h);
+    std::swap(h->beta, h->tmp);
+    if (mala) std::swap(h->gl, h->gltmp);
+    std::swap(h->ll, h->lltmp);
+  }
+  // ---- preconditioner from the reweighted cloud, then the moves targeting pi_t
+  tbeg(h, SPA_T_MOMENTS);
+  launch_moments(h->f64, h->beta, h->logw, h->N, h->p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
+                 h->stream);
+  tend(h);
+  launch_zero_int(h->acc, h->N, h->stream);
+  const double step_used = h->step;
+  for (int s = 0; s < h->sweeps; ++s)
+    if ((st = sweep(h, t_new, s, lam_new)) != SPA_OK) return st;
+  long long cnt = 0;
+  if ((st = read_count(h, &cnt)) != SPA_OK) return st;
+  if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
+  const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (static_cast<double>(h->N) * h->sweeps) : NAN;
+  if (h->sweeps > 0) adapt_step(h, acc_rate);
+  h->log_z += L;
+  h->t = t_new;
+  h->logz_path[t_new - 1] = h->log_z;
+  spa_smc_stats s{};
+  s.t = t_new;
+  s.resampled = resampled ? 1 : 0;
+  s.lambda = lam_new;
+  s.ess = ess;
+  s.log_z_inc = L;
+  s.log_z = h->log_z;
+  s.accept_rate = acc_rate;
+  s.step = step_used;
+  h->stats.push_back(s);
+  if (out) *out = s;
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  return SPA_OK;
+}
+
+static spa_status prep_operand(spa_smc *h, const void *beta, int M, int is_f64, Prec prec) {
+  spa_status st;
+  if ((st = ensure_xpack(h, prec)) != SPA_OK) return st;
+  const int PP = h->xp[static_cast<int>(prec)].PP;
+  const int Mpad = round_up(M, kPartPad);
+  OpScratch &o = h->scr[static_cast<int>(prec)];
+  if ((st = ensure_op(h, o, prec, PP, Mpad)) != SPA_OK) return st;
+  launch_pack_b(prec, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil, o.Bhi, o.Blo,
+                o.moff, o.yb, h->stream);
+  SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+static bool valid_prec(spa_prec p) { return p == SPA_PREC_FP64 || p == SPA_PREC_FP32 || p == SPA_PREC_BF16X2; }
+
+extern "C" spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
+                                     spa_prec prec, double *loglik_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!beta_dev || !loglik_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  if (!valid_prec(prec)) return set_err(h, SPA_ERR_ARG, "bad prec");
+  if (prec == SPA_PREC_FP64 && h->p > 255) return set_err(h, SPA_ERR_ARG, "FP64 path needs p <= 255");
+  const Prec P = to_prec(prec);
+  spa_status st;
+  if ((st = prep_operand(h, beta_dev, M, beta_is_fp64, P)) != SPA_OK) return st;
+  SPA_CK(h, launch_loglik(gemm_args(h, P, h->scr[static_cast<int>(P)], M, false, loglik_dev, nullptr), h->stream));
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_grad(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
+                                   double lambda, spa_prec prec, void *grad_dev, double *logpost_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!beta_dev || !grad_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return set_err(h, SPA_ERR_ARG, "lambda must be > 0");
+  if (!valid_prec(prec)) return set_err(h, SPA_ERR_ARG, "bad prec");
+  if (prec == SPA_PREC_FP64 && h->p > 255) return set_err(h, SPA_ERR_ARG, "FP64 path needs p <= 255");
+  const Prec P = to_prec(prec);
+  spa_status st;
+  if ((st = prep_operand(h, beta_dev, M, beta_is_fp64, P)) != SPA_OK) return st;
+  if (h->llscr_cap < (size_t)M) {
+    dfree(h, h->llscr);
+    h->llscr = nullptr;
+    if ((st = dalloc(h, &h->llscr, 8 * (size_t)M)) != SPA_OK) return st;
+    h->llscr_cap = M;
+  }
+  const bool native_f64 = P == Prec::F64;
+  void *gout = grad_dev;
+  if (native_f64 != (beta_is_fp64 != 0)) {   // contraction dtype differs from the caller's
+    const size_t need = (native_f64 ? 8 : 4) * (size_t)M * h->p;
+    if (h->gscr_cap < need) {
+      dfree(h, h->gscr);
+      h->gscr = nullptr;
+      if ((st = dalloc(h, &h->gscr, need)) != SPA_OK) return st;
+      h->gscr_cap = need;
+    }
+    gout = h->gscr;
+  }
+  SPA_CK(h, launch_loglik(gemm_args(h, P, h->scr[static_cast<int>(P)], M, true, h->llscr, gout), h->stream));
+  if (gout != grad_dev) launch_convert(native_f64, gout, grad_dev, (size_t)M * h->p, h->stream);
+  launch_add_prior(beta_is_fp64 != 0, beta_dev, M, h->p, make_prior(h, lambda), grad_dev, h->llscr, logpost_dev,
+                   h->stream);
+  SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_resample(spa_smc *h, const double *w_dev, int32_t M, uint32_t u32,
+                                       int32_t *ancestors_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!w_dev || !ancestors_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  if (M > (1 << 24)) return set_err(h, SPA_ERR_ARG, "M must be <= 2^24");
+  spa_status st;
+  if (h->cdf_cap < (size_t)M) {
+    dfree(h, h->cdf);
+    h->cdf = nullptr;
+    if ((st = dalloc(h, &h->cdf, 8 * (size_t)M)) != SPA_OK) return st;
+    h->cdf_cap = M;
+  }
+  LseArgs la{};
+  la.mode = 1;
+  la.M = M;
+  la.K = 53 - ceil_log2(M);
+  la.w = w_dev;
+  la.cdf = h->cdf;
+  la.anc = ancestors_dev;
+  la.scalars = h->scal;
+  la.u32 = u32;
+  launch_lse_resample(la, h->stream);
+  SPA_CK(h, hipGetLastError());
+  SPA_CK(h, hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  if (h->hscal[5] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "weights must be finite, >= 0 and not all zero");
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get(const spa_smc *h, const void **beta_dev, const double **logw_dev,
+                                  const double **mean_path_dev, const double **var_path_dev,
+                                  const double **logz_path_host, int32_t *t_out) {
+  if (!h) return SPA_ERR_ARG;
+  if (beta_dev) *beta_dev = h->beta;
+  if (logw_dev) *logw_dev = h->logw;
+  if (mean_path_dev) *mean_path_dev = h->mean_path;
+  if (var_path_dev) *var_path_dev = h->var_path;
+  if (logz_path_host) *logz_path_host = h->logz_path.data();
+  if (t_out) *t_out = h->t;
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get_stats(const spa_smc *h, int32_t t, spa_smc_stats *out) {
+  if (!h || !out) return SPA_ERR_ARG;
+  if (t < 1 || t > (int)h->stats.size()) return SPA_ERR_ARG;
+  *out = h->stats[t - 1];
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_set_state(spa_smc *h, const void *beta_dev, const double *logw_dev, int32_t t,
+                                        double step) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!beta_dev || !logw_dev) return set_err(h, SPA_ERR_ARG, "null pointer");
+  if (t < 1 || t > h->T) return set_err(h, SPA_ERR_ARG, "t out of range");
+  if (!(step > 0.0) || !std::isfinite(step)) return set_err(h, SPA_ERR_ARG, "step must be > 0");
+  SPA_CK(h, hipMemcpyAsync(h->beta, beta_dev, h->psz * (size_t)h->N * h->p, hipMemcpyDeviceToDevice, h->stream));
+  SPA_CK(h, hipMemcpyAsync(h->logw, logw_dev, 8 * (size_t)h->N, hipMemcpyDeviceToDevice, h->stream));
+  spa_status st;
+  if ((st = eval_state(h, h->beta, h->ll, h->gl)) != SPA_OK) return st;
+  // the log Z path before t is unknown for an injected state: restart the record at t
+  h->t = t;
+  h->step = step;
+  h->log_z = 0.0;
+  std::fill(h->logz_path.begin(), h->logz_path.end(), 0.0);
+  spa_smc_stats s{};
+  s.t = t;
+  s.lambda = h->lambda[t - 1];
+  s.ess = NAN;
+  s.accept_rate = NAN;
+  s.step = step;
+  h->stats.assign(t, s);
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uint64_t seed,
+                                        uint32_t *out_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!ctr_dev || !out_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  launch_philox(ctr_dev, M, static_cast<uint32_t>(seed & 0xFFFFFFFFull), static_cast<uint32_t>(seed >> 32),
+                out_dev, h->stream);
+  SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_set_timing(spa_smc *h, int32_t enable) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  h->timing = enable != 0;
+  for (int c = 0; c < SPA_TIMING_CLASSES; ++c) {
+    h->t_ms[c] = 0.0;
+    h->t_cnt[c] = 0;
+  }
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches) {
+  if (!h || !ms || !launches) return SPA_ERR_ARG;
+  for (int c = 0; c < SPA_TIMING_CLASSES; ++c) {
+    ms[c] = h->t_ms[c];
+    launches[c] = h->t_cnt[c];
+  }
+  return SPA_OK;
+}
+
+extern "C" void spa_smc_destroy(spa_smc *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->stream);
+  for (void *v : h->allocs) (void)hipFree(v);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->hscal) (void)hipHostFree(h->hscal);
+  if (h->hcount) (void)hipHostFree(h->hcount);
+  delete h;
+}
+
+extern "C" const char *spa_smc_last_error(const spa_smc *h) {
+  if (!h) return g_init_error.c_str();
+  return h->err.c_str();
+}

@@ -1,0 +1,745 @@
+// Bandwidth-bound kernels of the sampler: operand preparation, proposals, MH decisions,
+// incremental weights, logsumexp/ESS and systematic resampling, gathers and weighted
+// moments.  Row kernels map one wave64 to one particle (its p coefficients are contiguous,
+// so a wave reads a row with 16-byte lanes); reductions use fixed butterfly/tree orders.
+#include "spa_common.hpp"
+#include "spa_kernels.hpp"
+
+namespace spa {
+
+// ============================================================== operand preparation
+
+// Per-marker integer sums give exact mean, population variance and X_std^T y numerators:
+//   mu = S1/n, var = (n S2 - S1^2)/n^2, ytil = (n SY - S1 NY)/(n s).
+__global__ void col_stats_kernel(const uint8_t *__restrict__ X, const uint8_t *__restrict__ y,
+                                 int n, int p, double *mu, double *s, double *inv_s,
+                                 double *ytil, int *bad) {
+  const int j = blockIdx.x;
+  long long s1 = 0, s2 = 0, sy = 0, ny = 0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const long long v = X[(size_t)k * p + j];
+    const long long yk = y[k];
+    s1 += v;
+    s2 += v * v;
+    sy += v * yk;
+    ny += yk;
+  }
+  __shared__ long long red[4][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    s1 += __shfl_xor(s1, o, 64);
+    s2 += __shfl_xor(s2, o, 64);
+    sy += __shfl_xor(sy, o, 64);
+    ny += __shfl_xor(ny, o, 64);
+  }
+  if (lane == 0) {
+    red[w][0] = s1;
+    red[w][1] = s2;
+    red[w][2] = sy;
+    red[w][3] = ny;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s1 = red[0][0];
+    s2 = red[0][1];
+    sy = red[0][2];
+    ny = red[0][3];
+    for (int q = 1; q < (int)(blockDim.x >> 6); ++q) {
+      s1 += red[q][0];
+      s2 += red[q][1];
+      sy += red[q][2];
+      ny += red[q][3];
+    }
+    const double dn = static_cast<double>(n);
+    const long long num = (long long)n * s2 - s1 * s1;
+    const double var = static_cast<double>(num) / (dn * dn);
+    const double sd = sqrt(var);
+    mu[j] = static_cast<double>(s1) / dn;
+    s[j] = sd;
+    inv_s[j] = num > 0 ? 1.0 / sd : 0.0;
+    ytil[j] = num > 0 ? static_cast<double>((long long)n * sy - s1 * ny) / (dn * sd) : 0.0;
+    if (num <= 0) bad[0] = 1;
+  }
+}
+
+template <typename XT>
+__device__ __forceinline__ XT code_of(int v);
+template <>
+__device__ __forceinline__ double code_of<double>(int v) { return static_cast<double>(v); }
+template <>
+__device__ __forceinline__ float code_of<float>(int v) { return static_cast<float>(v); }
+template <>
+__device__ __forceinline__ __bf16 code_of<__bf16>(int v) { return static_cast<__bf16>(static_cast<float>(v)); }
+template <>
+__device__ __forceinline__ uint8_t code_of<uint8_t>(int v) {   // OCP e4m3: 0, 1.0, 2.0
+  return v == 0 ? 0x00 : (v == 1 ? 0x38 : 0x40);
+}
+
+// Genotypes in GEMM storage: Xk (n_pad x PP, individual-major) and Xt (PP x n_pad), with
+// an all-ones column at PP-1 for real individuals and zeros elsewhere in the padding.
+template <typename XT>
+__global__ void pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad, int PP,
+                              XT *__restrict__ Xk, XT *__restrict__ Xt) {
+  const size_t total = (size_t)n_pad * PP;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int k = static_cast<int>(idx / PP), j = static_cast<int>(idx % PP);
+    int v = 0;
+    if (k < n) v = (j < p) ? X[(size_t)k * p + j] : (j == PP - 1 ? 1 : 0);
+    const XT c = code_of<XT>(v);
+    Xk[idx] = c;
+    Xt[(size_t)j * n_pad + k] = c;
+  }
+}
+
+template <typename ET>
+__global__ void labels_kernel(const uint8_t *__restrict__ y, int n, int n_pad, ET *__restrict__ yv) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_pad) yv[k] = (k < n) ? static_cast<ET>(y[k]) : ET(0);
+}
+
+// ------------------------------------------------- scaled-coefficient operand b = beta/s
+// Writes the B operand of the contraction for one row (already in registers as 4
+// consecutive coefficients per lane) and returns (m, yb) contributions.
+template <Prec P>
+struct BPack;
+
+template <>
+struct BPack<Prec::BF16X2> {
+  using BT = __bf16;
+  __device__ static void put(double bj, BT *hi, BT *lo, size_t off, double &used) {
+    const float f = static_cast<float>(bj);
+    const __bf16 h = static_cast<__bf16>(f);
+    const __bf16 l = static_cast<__bf16>(f - static_cast<float>(h));
+    hi[off] = h;
+    lo[off] = l;
+    used = static_cast<double>(static_cast<float>(h)) + static_cast<double>(static_cast<float>(l));
+  }
+};
+template <>
+struct BPack<Prec::F32> {
+  using BT = float;
+  __device__ static void put(double bj, BT *hi, BT *, size_t off, double &used) {
+    const float f = static_cast<float>(bj);
+    hi[off] = f;
+    used = static_cast<double>(f);
+  }
+};
+template <>
+struct BPack<Prec::F64> {
+  using BT = double;
+  __device__ static void put(double bj, BT *hi, BT *, size_t off, double &used) {
+    hi[off] = bj;
+    used = bj;
+  }
+};
+
+struct ColConst {
+  const double *mu, *s, *inv_s, *ytil;   // PP-padded
+};
+
+// Pack an arbitrary particle matrix (dtype IT) into the B operand of precision P.
+template <Prec P, typename IT>
+__global__ void pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int p, int PP,
+                              ColConst cc, void *Bhi_, void *Blo_, double *__restrict__ moff,
+                              double *__restrict__ yb) {
+  using BT = typename BPack<P>::BT;
+  BT *Bhi = reinterpret_cast<BT *>(Bhi_);
+  BT *Blo = reinterpret_cast<BT *>(Blo_);
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= M_pad) return;
+  double m = 0.0, ybv = 0.0;
+  for (int j = lane; j < PP; j += 64) {
+    const double bj = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * cc.inv_s[j] : 0.0;
+    double used;
+    BPack<P>::put(bj, Bhi, Blo, (size_t)i * PP + j, used);
+    m += cc.mu[j] * used;
+    ybv += cc.ytil[j] * cc.s[j] * used;
+  }
+  m = wave_sum(m);
+  ybv = wave_sum(ybv);
+  if (lane == 0) {
+    moff[i] = m;
+    yb[i] = ybv;
+  }
+}
+
+// ================================================================ move kernels
+
+// One proposal sweep: beta' from beta (random walk or MALA), the B operand of beta',
+// and per-particle log prior terms.  Lane l handles markers 4l..4l+3 (one Philox block).
+template <Prec P, typename PT, bool MALA>
+__global__ void propose_kernel(ProposeArgs a) {
+  using BT = typename BPack<P>::BT;
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= a.M_pad) return;
+  const PT *beta = reinterpret_cast<const PT *>(a.beta);
+  const PT *gl = reinterpret_cast<const PT *>(a.gl);
+  PT *prop = reinterpret_cast<PT *>(a.prop);
+  BT *Bhi = reinterpret_cast<BT *>(a.Bhi);
+  BT *Blo = reinterpret_cast<BT *>(a.Blo);
+  const int p = a.p, PP = a.PP;
+  const bool live = i < a.M;
+  double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
+  const Prior pr = a.prior;
+  for (int b0 = lane * 4; b0 < PP; b0 += 256) {
+    PT z[4] = {0, 0, 0, 0};
+    if (live && b0 < p) {
+      const uint4 w = philox4x32_10(
+          make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(b0 >> 2), a.sweep,
+                     word3(a.t, kTagNormal)),
+          a.k0, a.k1);
+      box_muller(w.x, w.y, z[0], z[1]);
+      box_muller(w.z, w.w, z[2], z[3]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = b0 + q;
+      double bj = 0.0;
+      if (live && j < p) {
+        const size_t off = (size_t)i * p + j;
+        const double cur = static_cast<double>(beta[off]);
+        const double sg = a.sigma[j];
+        PT nv;
+        double meanf = cur;
+        if constexpr (MALA) {
+          const double g = static_cast<double>(gl[off]) + gt_grad(cur, pr);
+          meanf = cur + 0.5 * a.step * sg * sg * g;
+          nv = static_cast<PT>(meanf + a.sqrt_step * sg * static_cast<double>(z[q]));
+        } else {
+          nv = static_cast<PT>(cur + a.step * sg * static_cast<double>(z[q]));
+        }
+        prop[off] = nv;
+        const double nvd = static_cast<double>(nv);
+        if constexpr (MALA) {
+          const double d = nvd - meanf;
+          lqf -= d * d / (2.0 * a.step * sg * sg);
+        }
+        lpc += gt_logpdf(cur, pr);
+        lpp += gt_logpdf(nvd, pr);
+        bj = nvd * a.cc.inv_s[j];
+      }
+      if (j < PP) {
+        double used;
+        BPack<P>::put(bj, Bhi, Blo, (size_t)i * PP + j, used);
+        m += a.cc.mu[j] * used;
+        ybv += a.cc.ytil[j] * a.cc.s[j] * used;
+      }
+    }
+  }
+  m = wave_sum(m);
+  ybv = wave_sum(ybv);
+  lpc = wave_sum(lpc);
+  lpp = wave_sum(lpp);
+  if constexpr (MALA) lqf = wave_sum(lqf);
+  if (lane == 0) {
+    a.moff[i] = m;
+    a.yb[i] = ybv;
+    if (live) {
+      a.lp_cur[i] = lpc;
+      a.lp_prop[i] = lpp;
+      a.lqf[i] = lqf;
+    }
+  }
+}
+
+// Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
+template <typename PT, bool MALA>
+__global__ void accept_kernel(AcceptArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= a.M) return;
+  PT *beta = reinterpret_cast<PT *>(a.beta);
+  PT *gl = reinterpret_cast<PT *>(a.gl);
+  const PT *prop = reinterpret_cast<const PT *>(a.prop);
+  const PT *glp = reinterpret_cast<const PT *>(a.gl_prop);
+  const int p = a.p;
+  const Prior pr = a.prior;
+  double lqr = 0.0;
+  if constexpr (MALA) {
+    for (int j = lane; j < p; j += 64) {
+      const size_t off = (size_t)i * p + j;
+      const double nv = static_cast<double>(prop[off]);
+      const double sg = a.sigma[j];
+      const double g = static_cast<double>(glp[off]) + gt_grad(nv, pr);
+      const double meanr = nv + 0.5 * a.step * sg * sg * g;
+      const double d = static_cast<double>(beta[off]) - meanr;
+      lqr -= d * d / (2.0 * a.step * sg * sg);
+    }
+    lqr = wave_sum(lqr);
+  }
+  const double log_alpha = a.ll_prop[i] - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
+  const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
+                                a.k0, a.k1);
+  const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
+  const bool acc = log(u) < log_alpha;   // false for NaN
+  if (acc) {
+    for (int j = lane; j < p; j += 64) {
+      const size_t off = (size_t)i * p + j;
+      beta[off] = prop[off];
+      if constexpr (MALA) gl[off] = glp[off];
+    }
+    if (lane == 0) a.ll[i] = a.ll_prop[i];
+  }
+  if (lane == 0) a.acc_cnt[i] += acc ? 1 : 0;
+}
+
+// ================================================================ weights
+
+// logw_i += sum_j [log Gt(beta_ij | a, lam_new) - log Gt(beta_ij | a, lam_old)], written as
+// a log(r) - (a+1) log((a lam_new + |b|)/(a lam_old + |b|)) per coefficient, r = lam_new/lam_old
+// (and log(1/r) - |b| (1/lam_new - 1/lam_old) for the double exponential).
+template <typename PT>
+__global__ void reweight_kernel(const PT *__restrict__ beta, int M, int p, double a, int a_inf,
+                                double lam_new, double lam_old, double *__restrict__ logw) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= M) return;
+  const double lr = log(lam_new / lam_old);
+  double d = 0.0;
+  if (a_inf) {
+    const double dl = 1.0 / lam_new - 1.0 / lam_old;
+    for (int j = lane; j < p; j += 64) d += -lr - fabs(static_cast<double>(beta[(size_t)i * p + j])) * dl;
+  } else {
+    const double an = a * lam_new, ao = a * lam_old;
+    for (int j = lane; j < p; j += 64) {
+      const double x = fabs(static_cast<double>(beta[(size_t)i * p + j]));
+      d += a * lr - (a + 1.0) * log((an + x) / (ao + x));
+    }
+  }
+  d = wave_sum(d);
+  if (lane == 0) logw[i] += d;
+}
+
+// ---- single-workgroup reductions (1024 threads, fixed order)
+constexpr int kRB = 1024;
+
+__device__ double block_max(double v, double *sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int q = 1; q < kRB / 64; ++q) r = fmax(r, sh[q]);
+  return r;
+}
+__device__ double block_sum(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int q = 1; q < kRB / 64; ++q) r += sh[q];
+  return r;
+}
+
+// Normalisation, log Z increment, ESS and (if triggered, or always in weight mode)
+// systematic resampling of the quantised CDF.
+//  mode 0: input logw (log weights relative to the normalised logW_{t-1}); writes the
+//          normalised logW, scalars {ESS, L, resampled, max}, and ancestors if
+//          ESS < ess_frac * M (then logW = -log M).
+//  mode 1: input linear weights w; validates them; always resamples.
+// The CDF is over q_i = floor((w_i / max w) 2^K), K = 53 - ceil(log2 M): integer partial
+// sums below 2^53 are exact in FP64 in any order, so the scan is bit-exact.
+__global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
+  __shared__ double sh[kRB / 64];
+  __shared__ double tot[kRB];
+  const int M = a.M;
+  const int per = (M + kRB - 1) / kRB;
+  const int lo = min(M, threadIdx.x * per), hi = min(M, lo + per);
+  double *lw = a.logw;
+  int do_resample = 1;
+  if (a.mode == 0) {
+    double m = -INFINITY;
+    for (int i = lo; i < hi; ++i) m = fmax(m, lw[i]);
+    m = block_max(m, sh);
+    double s1 = 0.0;
+    for (int i = lo; i < hi; ++i) s1 += exp(lw[i] - m);
+    s1 = block_sum(s1, sh);
+    const double L = m + log(s1);
+    double s2 = 0.0;
+    for (int i = lo; i < hi; ++i) {
+      const double v = lw[i] - L;
+      lw[i] = v;
+      const double W = exp(v);
+      s2 += W * W;
+    }
+    s2 = block_sum(s2, sh);
+    const double ess = 1.0 / s2;
+    do_resample = ess < a.ess_frac * static_cast<double>(M);
+    if (threadIdx.x == 0) {
+      a.scalars[0] = ess;
+      a.scalars[1] = L;
+      a.scalars[2] = do_resample ? 1.0 : 0.0;
+      a.scalars[3] = m;
+      a.scalars[4] = (isfinite(L) && isfinite(ess)) ? 0.0 : 1.0;
+    }
+    if (!(isfinite(L) && isfinite(ess))) return;
+    if (!do_resample) return;
+  }
+  // ---- weights and their maximum
+  const double *wsrc = a.w;   // mode 1 input
+  double wmax = -INFINITY;
+  int badw = 0;
+  for (int i = lo; i < hi; ++i) {
+    const double w = (a.mode == 0) ? exp(lw[i]) : wsrc[i];
+    if (!(w >= 0.0) || isinf(w)) badw = 1;
+    wmax = fmax(wmax, w);
+  }
+  wmax = block_max(wmax, sh);
+  const double anybad = block_max(badw ? 1.0 : 0.0, sh);
+  if (anybad != 0.0 || !(wmax > 0.0)) {
+    if (threadIdx.x == 0) a.scalars[5] = 1.0;   // invalid weights: nothing written
+    return;
+  }
+  const double scale = ldexp(1.0, a.K);
+  // ---- local inclusive sums of the quantised weights, then an exclusive block scan
+  double run = 0.0;
+  for (int i = lo; i < hi; ++i) {
+    const double w = (a.mode == 0) ? exp(lw[i]) : wsrc[i];
+    run += floor((w / wmax) * scale);
+    a.cdf[i] = run;
+  }
+  tot[threadIdx.x] = run;
+  __syncthreads();
+  for (int o = 1; o < kRB; o <<= 1) {    // Hillis-Steele inclusive scan of the totals
+    const double v = (threadIdx.x >= (unsigned)o) ? tot[threadIdx.x - o] : 0.0;
+    __syncthreads();
+    tot[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const double base = (threadIdx.x > 0) ? tot[threadIdx.x - 1] : 0.0;
+  for (int i = lo; i < hi; ++i) a.cdf[i] += base;
+  __syncthreads();
+  __threadfence_block();
+  const double C = tot[kRB - 1];
+  // ---- offspring positions and binary search (no fused multiply-add)
+  const double U = static_cast<double>(a.u32) * 0x1p-32;
+  const double dM = static_cast<double>(M);
+  for (int i = lo; i < hi; ++i) {
+    const double num = __dadd_rn(static_cast<double>(i), U);
+    const double tpos = __dmul_rn(__ddiv_rn(num, dM), C);
+    int l = 0, r = M;   // first k with cdf[k] > tpos
+    while (l < r) {
+      const int mid = (l + r) >> 1;
+      if (a.cdf[mid] > tpos) r = mid;
+      else l = mid + 1;
+    }
+    a.anc[i] = min(l, M - 1);
+  }
+  if (a.mode == 0) {
+    const double lN = -log(dM);
+    for (int i = lo; i < hi; ++i) lw[i] = lN;
+  }
+  if (threadIdx.x == 0) a.scalars[5] = 0.0;
+}
+
+template <typename PT>
+__global__ void gather_kernel(const int *__restrict__ anc, int M, int p, const PT *__restrict__ src,
+                              PT *__restrict__ dst, const PT *__restrict__ gsrc, PT *__restrict__ gdst,
+                              const double *__restrict__ llsrc, double *__restrict__ lldst) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= M) return;
+  const size_t k = static_cast<size_t>(anc[i]);
+  for (int j = lane; j < p; j += 64) {
+    dst[(size_t)i * p + j] = src[k * p + j];
+    if (gsrc) gdst[(size_t)i * p + j] = gsrc[k * p + j];
+  }
+  if (lane == 0) lldst[i] = llsrc[k];
+}
+
+// ---- weighted moments per coefficient (two kernels: chunk partials, ordered combine).
+// Partial sums are shifted by the first particle's row (removes cancellation):
+//   S0 = sum W, S1_j = sum W (b_ij - c_j), S2_j = sum W (b_ij - c_j)^2.
+template <typename PT>
+__global__ void moments_partial_kernel(const PT *__restrict__ beta, const double *__restrict__ logw,
+                                       int M, int p, int rows_per_chunk, double *__restrict__ part) {
+  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int rg = threadIdx.x >> 6;   // 4 row groups
+  const int chunk = blockIdx.y;
+  const int r0 = chunk * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  const double c = (col < p) ? static_cast<double>(beta[col]) : 0.0;
+  for (int i = r0 + rg; i < r1; i += 4) {
+    const double W = exp(logw[i]);
+    s0 += W;
+    if (col < p) {
+      const double d = static_cast<double>(beta[(size_t)i * p + col]) - c;
+      s1 += W * d;
+      s2 += W * d * d;
+    }
+  }
+  __shared__ double sh[3][4][64];
+  sh[0][rg][threadIdx.x & 63] = s0;
+  sh[1][rg][threadIdx.x & 63] = s1;
+  sh[2][rg][threadIdx.x & 63] = s2;
+  __syncthreads();
+  if (rg == 0 && col < p) {
+    const int l = threadIdx.x & 63;
+    double t0 = sh[0][0][l], t1 = sh[1][0][l], t2 = sh[2][0][l];
+    for (int q = 1; q < 4; ++q) {
+      t0 += sh[0][q][l];
+      t1 += sh[1][q][l];
+      t2 += sh[2][q][l];
+    }
+    double *o = part + ((size_t)chunk * p + col) * 3;
+    o[0] = t0;
+    o[1] = t1;
+    o[2] = t2;
+  }
+}
+
+template <typename PT>
+__global__ void moments_final_kernel(const PT *__restrict__ beta, const double *__restrict__ part,
+                                     int nchunks, int p, double *__restrict__ mean,
+                                     double *__restrict__ var, double *__restrict__ sigma,
+                                     double sigma_floor) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= p) return;
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  for (int c = 0; c < nchunks; ++c) {
+    const double *o = part + ((size_t)c * p + j) * 3;
+    t0 += o[0];
+    t1 += o[1];
+    t2 += o[2];
+  }
+  const double d1 = t1 / t0;
+  const double m = static_cast<double>(beta[j]) + d1;
+  const double v = fmax(t2 / t0 - d1 * d1, 0.0);
+  if (mean) mean[j] = m;
+  if (var) var[j] = v;
+  if (sigma) sigma[j] = sqrt(fmax(v, sigma_floor * sigma_floor));
+}
+
+__global__ void count_kernel(const int *__restrict__ cnt, int M, long long *__restrict__ out) {
+  __shared__ long long sh[16];
+  long long s = 0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) s += cnt[i];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long r = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) r += sh[q];
+    out[0] = r;
+  }
+}
+
+__global__ void fill_kernel(double *__restrict__ x, int n, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+__global__ void zero_int_kernel(int *__restrict__ x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0;
+}
+
+template <typename ST, typename DT>
+__global__ void convert_kernel(const ST *__restrict__ src, DT *__restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = static_cast<DT>(src[i]);
+}
+
+// log posterior = loglik + sum_j log Gt(beta_ij); gradient += prior gradient (in place).
+template <typename PT>
+__global__ void add_prior_kernel(const PT *__restrict__ beta, int M, int p, Prior pr,
+                                 PT *__restrict__ g, const double *__restrict__ ll,
+                                 double *__restrict__ logpost) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= M) return;
+  double lp = 0.0;
+  for (int j = lane; j < p; j += 64) {
+    const size_t off = (size_t)i * p + j;
+    const double b = static_cast<double>(beta[off]);
+    if (g) g[off] = static_cast<PT>(static_cast<double>(g[off]) + gt_grad(b, pr));
+    lp += gt_logpdf(b, pr);
+  }
+  lp = wave_sum(lp);
+  if (lane == 0 && logpost) logpost[i] = ll[i] + lp;
+}
+
+__global__ void philox_kernel(const uint32_t *__restrict__ ctr, int M, uint32_t k0, uint32_t k1,
+                              uint32_t *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+  const uint4 r = philox4x32_10(c, k0, k1);
+  out[4 * i] = r.x;
+  out[4 * i + 1] = r.y;
+  out[4 * i + 2] = r.z;
+  out[4 * i + 3] = r.w;
+}
+
+// ================================================================ host launchers
+
+static inline int grid_rows(int rows, int rows_per_block) { return (rows + rows_per_block - 1) / rows_per_block; }
+
+void launch_col_stats(const uint8_t *X, const uint8_t *y, int n, int p, double *mu, double *s,
+                      double *inv_s, double *ytil, int *bad, hipStream_t st) {
+  hipLaunchKernelGGL(col_stats_kernel, dim3(p), dim3(256), 0, st, X, y, n, p, mu, s, inv_s, ytil, bad);
+}
+
+void launch_pack_x(XFormat f, const uint8_t *X, int n, int p, int n_pad, int PP, void *Xk, void *Xt,
+                   hipStream_t st) {
+  const size_t total = (size_t)n_pad * PP;
+  const int grid = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
+  switch (f) {
+    case XFormat::F64:
+      hipLaunchKernelGGL(pack_x_kernel<double>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+                         (double *)Xk, (double *)Xt);
+      break;
+    case XFormat::F32:
+      hipLaunchKernelGGL(pack_x_kernel<float>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+                         (float *)Xk, (float *)Xt);
+      break;
+    case XFormat::BF16:
+      hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+                         (__bf16 *)Xk, (__bf16 *)Xt);
+      break;
+    case XFormat::FP8:
+      hipLaunchKernelGGL(pack_x_kernel<uint8_t>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+                         (uint8_t *)Xk, (uint8_t *)Xt);
+      break;
+  }
+}
+
+void launch_labels(const uint8_t *y, int n, int n_pad, bool f64, void *yv, hipStream_t st) {
+  if (f64)
+    hipLaunchKernelGGL(labels_kernel<double>, dim3((n_pad + 255) / 256), dim3(256), 0, st, y, n, n_pad, (double *)yv);
+  else
+    hipLaunchKernelGGL(labels_kernel<float>, dim3((n_pad + 255) / 256), dim3(256), 0, st, y, n, n_pad, (float *)yv);
+}
+
+void launch_pack_b(Prec prec, bool in_f64, const void *beta, int M, int M_pad, int p, int PP,
+                   const double *mu, const double *s, const double *inv_s, const double *ytil,
+                   void *Bhi, void *Blo, double *moff, double *yb, hipStream_t st) {
+  ColConst cc{mu, s, inv_s, ytil};
+  const int grid = grid_rows(M_pad, 4);
+#define SPA_PACK(P, IT)                                                                       \
+  hipLaunchKernelGGL((pack_b_kernel<P, IT>), dim3(grid), dim3(256), 0, st, (const IT *)beta, M, \
+                     M_pad, p, PP, cc, Bhi, Blo, moff, yb)
+  if (prec == Prec::BF16X2) {
+    if (in_f64) SPA_PACK(Prec::BF16X2, double); else SPA_PACK(Prec::BF16X2, float);
+  } else if (prec == Prec::F32) {
+    if (in_f64) SPA_PACK(Prec::F32, double); else SPA_PACK(Prec::F32, float);
+  } else {
+    if (in_f64) SPA_PACK(Prec::F64, double); else SPA_PACK(Prec::F64, float);
+  }
+#undef SPA_PACK
+}
+
+void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) {
+  const int grid = grid_rows(a.M_pad, 4);
+#define SPA_PROP(P, PT, MA) hipLaunchKernelGGL((propose_kernel<P, PT, MA>), dim3(grid), dim3(256), 0, st, a)
+  if (prec == Prec::F64) {
+    if (mala) SPA_PROP(Prec::F64, double, true); else SPA_PROP(Prec::F64, double, false);
+  } else if (prec == Prec::F32) {
+    if (mala) SPA_PROP(Prec::F32, float, true); else SPA_PROP(Prec::F32, float, false);
+  } else {
+    if (mala) SPA_PROP(Prec::BF16X2, float, true); else SPA_PROP(Prec::BF16X2, float, false);
+  }
+#undef SPA_PROP
+}
+
+void launch_accept(bool f64, bool mala, const AcceptArgs &a, hipStream_t st) {
+  const int grid = grid_rows(a.M, 4);
+  if (f64) {
+    if (mala) hipLaunchKernelGGL((accept_kernel<double, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((accept_kernel<double, false>), dim3(grid), dim3(256), 0, st, a);
+  } else {
+    if (mala) hipLaunchKernelGGL((accept_kernel<float, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((accept_kernel<float, false>), dim3(grid), dim3(256), 0, st, a);
+  }
+}
+
+void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,
+                     double lam_old, double *logw, hipStream_t st) {
+  const int grid = grid_rows(M, 4);
+  if (f64)
+    hipLaunchKernelGGL(reweight_kernel<double>, dim3(grid), dim3(256), 0, st, (const double *)beta, M, p, a,
+                       a_inf, lam_new, lam_old, logw);
+  else
+    hipLaunchKernelGGL(reweight_kernel<float>, dim3(grid), dim3(256), 0, st, (const float *)beta, M, p, a,
+                       a_inf, lam_new, lam_old, logw);
+}
+
+void launch_lse_resample(const LseArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(lse_resample_kernel, dim3(1), dim3(kRB), 0, st, a);
+}
+
+void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void *dst, const void *gsrc,
+                   void *gdst, const double *llsrc, double *lldst, hipStream_t st) {
+  const int grid = grid_rows(M, 4);
+  if (f64)
+    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid), dim3(256), 0, st, anc, M, p, (const double *)src,
+                       (double *)dst, (const double *)gsrc, (double *)gdst, llsrc, lldst);
+  else
+    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid), dim3(256), 0, st, anc, M, p, (const float *)src,
+                       (float *)dst, (const float *)gsrc, (float *)gdst, llsrc, lldst);
+}
+
+int moments_chunks(int M) { return std::max(1, std::min(256, (M + 255) / 256)); }
+
+void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
+                    double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st) {
+  const int nch = moments_chunks(M);
+  const int rpc = (M + nch - 1) / nch;
+  dim3 grid((p + 63) / 64, nch);
+  if (f64) {
+    hipLaunchKernelGGL(moments_partial_kernel<double>, grid, dim3(256), 0, st, (const double *)beta, logw, M, p,
+                       rpc, part);
+    hipLaunchKernelGGL(moments_final_kernel<double>, dim3((p + 255) / 256), dim3(256), 0, st,
+                       (const double *)beta, part, nch, p, mean, var, sigma, sigma_floor);
+  } else {
+    hipLaunchKernelGGL(moments_partial_kernel<float>, grid, dim3(256), 0, st, (const float *)beta, logw, M, p,
+                       rpc, part);
+    hipLaunchKernelGGL(moments_final_kernel<float>, dim3((p + 255) / 256), dim3(256), 0, st,
+                       (const float *)beta, part, nch, p, mean, var, sigma, sigma_floor);
+  }
+}
+
+void launch_count(const int *cnt, int M, long long *out, hipStream_t st) {
+  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1024), 0, st, cnt, M, out);
+}
+
+void launch_fill(double *x, int n, double v, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, v);
+}
+void launch_zero_int(int *x, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n);
+}
+
+void launch_convert(bool src_f64, const void *src, void *dst, size_t n, hipStream_t st) {
+  const int grid = static_cast<int>(std::min<size_t>((n + 255) / 256, 65535));
+  if (src_f64)
+    hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid), dim3(256), 0, st, (const double *)src,
+                       (float *)dst, n);
+  else
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid), dim3(256), 0, st, (const float *)src,
+                       (double *)dst, n);
+}
+
+void launch_add_prior(bool f64, const void *beta, int M, int p, const Prior &pr, void *g, const double *ll,
+                      double *logpost, hipStream_t st) {
+  const int grid = grid_rows(M, 4);
+  if (f64)
+    hipLaunchKernelGGL(add_prior_kernel<double>, dim3(grid), dim3(256), 0, st, (const double *)beta, M, p, pr,
+                       (double *)g, ll, logpost);
+  else
+    hipLaunchKernelGGL(add_prior_kernel<float>, dim3(grid), dim3(256), 0, st, (const float *)beta, M, p, pr,
+                       (float *)g, ll, logpost);
+}
+
+void launch_philox(const uint32_t *ctr, int M, uint32_t k0, uint32_t k1, uint32_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(philox_kernel, dim3((M + 255) / 256), dim3(256), 0, st, ctr, M, k0, k1, out);
+}
+
+}  // namespace spa

@@ -16,3 +16,25 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+def pytest_runtest_logstart(nodeid, location):
+    """Name every GPU case on stderr before it runs (flushed), so a run that ends the box
+    still says which case was running."""
+    if "gpu" in nodeid:
+        sys.__stderr__.write(f"\n[start] {nodeid}\n")
+        sys.__stderr__.flush()
+
+
+def pytest_collection_modifyitems(config, items):
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        return
+    skip = pytest.mark.skip(reason="needs a GPU")
+    for it in items:
+        if "gpu" in it.keywords:
+            it.add_marker(skip)

@@ -1,0 +1,191 @@
+"""GPU parity of the whole sampler (init/step) against the FP64 oracle.
+
+* one step from an identical state: weights, ESS, log Z increment, resampling decision
+  and ancestors (through the gathered particles), moments -- to round-off;
+* FP64 end to end: both sides share the Philox streams, so with FP64 everywhere the
+  GPU trajectory tracks the oracle's to round-off;
+* reduced precision and MALA: posterior-mean and log Z paths agree within Monte Carlo
+  error over independent seeds;
+* full-size workloads (n=5000/p=200/N=16384 MALA, n=10000/p=500/N=32768): sampled
+  per-particle log-likelihoods and gradients of the live particle system."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import gt_prior, likelihood, philox, smc
+from synth import CONFIGS, make_dataset
+from tests.gpu_util import dataset, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _gpu(cfg, X, y, **over):
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    return SpaSMC(SamplerConfig.from_workload(cfg, n=X.shape[0], p=X.shape[1], **over), X, y)
+
+
+def _oracle_problem(cfg, X, y):
+    Xs, _, _ = likelihood.standardise(X)
+    return smc.Problem(Xs=Xs, y=y.astype(np.float64), a=cfg.a)
+
+
+@pytest.mark.parametrize("t", [8, 13, 14, 17])
+def test_one_step_weights_and_resampling_fp64(t):
+    torch = _torch()
+    cfg, X, y, Xs = dataset("cfg0")
+    prob = _oracle_problem(cfg, X, y)
+    lam = cfg.grid()
+    res = smc.run_smc(prob, lam, cfg.N, "rwm", cfg.sweeps, cfg.init_sweeps, cfg.ess_frac,
+                      cfg.step0(), cfg.seed, snapshot_at=(t,), T_stop=t)
+    st = res.snapshots[t]
+    g = _gpu(cfg, X, y, sweeps=0, init_sweeps=0)
+    g.set_state(torch.from_numpy(st.beta), torch.from_numpy(st.logW), t, 1.0)
+    out = g.step()
+    # oracle step t -> t+1 without moves
+    delta = smc.reweight_delta(st.beta, cfg.a, lam[t], lam[t - 1])
+    logW, L = smc.normalise(st.logW + delta)
+    e = smc.ess(logW)
+    beta = st.beta
+    resampled = e < cfg.ess_frac * cfg.N
+    if resampled:
+        anc = smc.systematic_resample(np.exp(logW), philox.resample_u32(cfg.seed, t + 1))
+        beta = beta[anc]
+        logW = np.full(cfg.N, -math.log(cfg.N))
+    assert out["resampled"] == resampled
+    assert abs(out["ess"] - e) <= 1e-11 * e
+    assert abs(out["log_z_inc"] - L) <= 1e-11 * max(1.0, abs(L))
+    gb, glw = g.particles()
+    assert np.array_equal(gb.cpu().numpy(), beta)          # gathered rows, bit for bit
+    assert np.allclose(glw.cpu().numpy(), logW, rtol=0, atol=1e-11)
+    mean, var, _ = g.paths()
+    m_ref, v_ref = smc.weighted_moments(beta, logW)
+    assert np.allclose(mean[t], m_ref, rtol=1e-10, atol=1e-13)
+    assert np.allclose(var[t], v_ref, rtol=1e-9, atol=1e-15)
+
+
+def test_one_step_with_moves_fp64():
+    torch = _torch()
+    cfg, X, y, Xs = dataset("cfg0")
+    prob = _oracle_problem(cfg, X, y)
+    lam, t = cfg.grid(), 10
+    res = smc.run_smc(prob, lam, cfg.N, "rwm", cfg.sweeps, cfg.init_sweeps, cfg.ess_frac,
+                      cfg.step0(), cfg.seed, snapshot_at=(t,), T_stop=t)
+    st, step = res.snapshots[t], res.step[t - 1]
+    g = _gpu(cfg, X, y, init_sweeps=0)
+    g.set_state(torch.from_numpy(st.beta), torch.from_numpy(st.logW), t, step)
+    out = g.step()
+    # the oracle's step t -> t+1 from the same state
+    o = smc.State(beta=st.beta.copy(), ll=prob.loglik(st.beta), gl=np.zeros_like(st.beta),
+                  logW=st.logW.copy())
+    o.logW, L = smc.normalise(o.logW + smc.reweight_delta(o.beta, cfg.a, lam[t], lam[t - 1]))
+    if smc.ess(o.logW) < cfg.ess_frac * cfg.N:
+        anc = smc.systematic_resample(np.exp(o.logW), philox.resample_u32(cfg.seed, t + 1))
+        o.beta, o.ll = o.beta[anc], o.ll[anc]
+        o.logW = np.full(cfg.N, -math.log(cfg.N))
+    sigma = np.sqrt(np.maximum(smc.weighted_moments(o.beta, o.logW)[1], 1e-24))
+    acc = sum(smc.rwm_sweep(prob, o, lam[t], step, sigma, cfg.seed, s, t + 1) for s in range(cfg.sweeps))
+    gb = g.particles()[0].cpu().numpy()
+    rows_differ = np.any(np.abs(gb - o.beta) > 1e-9, axis=1)
+    print(f"rows differing: {rows_differ.sum()} of {cfg.N}; accept gpu {out['accept_rate']:.4f} "
+          f"oracle {acc / (cfg.N * cfg.sweeps):.4f}")
+    assert rows_differ.sum() <= 2      # a decision within round-off of log u may flip
+    assert np.allclose(gb[~rows_differ], o.beta[~rows_differ], rtol=0, atol=1e-11)
+
+
+def test_full_sweep_fp64_tracks_oracle():
+    cfg, X, y, Xs = dataset("cfg0")
+    r = smc.run_config(cfg, X, y)
+    g = _gpu(cfg, X, y)
+    stats = g.run()
+    mean, var, logz = g.paths()
+    d = np.abs(mean - r.mean)
+    print(f"mean path max abs diff {d.max():.3e}; log Z max diff {np.abs(logz - r.log_z).max():.3e}")
+    assert d.max() <= 1e-8
+    assert np.allclose(logz, r.log_z, rtol=1e-10, atol=1e-9)
+    assert [s["resampled"] for s in stats] == list(r.resampled)
+    assert np.allclose([s["ess"] for s in stats], r.ess, rtol=1e-9)
+
+
+def stat_compare(gpu, orc):
+    """Per-cell Welch z of replicate means; returns (max |z|, fraction |z| > 3, rms z)."""
+    mg, mo = gpu.mean(0), orc.mean(0)
+    vg, vo = gpu.var(0, ddof=1) / gpu.shape[0], orc.var(0, ddof=1) / orc.shape[0]
+    z = (mg - mo) / np.sqrt(vg + vo + 1e-30)
+    return np.abs(z).max(), np.mean(np.abs(z) > 3.0), np.sqrt(np.mean(z * z))
+
+
+@pytest.mark.parametrize("name,over,Rg,Ro", [
+    ("cfg1", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("cfg2", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("cfg3", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+])
+def test_statistical_parity(name, over, Rg, Ro):
+    """Independent seeds on both sides; posterior means and log Z within MC error."""
+    cfg0 = CONFIGS[name].replace(**over)
+    n, p = (2000, 50) if name == "cfg3" else (None, None)
+    d = make_dataset(cfg0, n=n, p=p)
+    X, y = d.X, d.y
+    cfg = cfg0.replace(n=X.shape[0], p=X.shape[1])
+    gm, gz, om, oz = [], [], [], []
+    for r in range(Rg):
+        g = _gpu(cfg, X, y, seed=1000 + r)
+        g.run()
+        m, _, lz = g.paths()
+        gm.append(m)
+        gz.append(lz)
+        g.close()
+    for r in range(Ro):
+        res = smc.run_config(cfg, X, y, seed=2000 + r)
+        om.append(res.mean)
+        oz.append(res.log_z)
+    zmax, frac3, rms = stat_compare(np.stack(gm), np.stack(om))
+    print(f"{name}: means max|z| {zmax:.2f}, frac>3 {frac3:.3f}, rms {rms:.2f}")
+    assert zmax <= 8.0 and frac3 <= 0.05 and rms <= 1.6
+    zmax, frac3, rms = stat_compare(np.stack(gz)[:, 1:], np.stack(oz)[:, 1:])
+    print(f"{name}: log Z max|z| {zmax:.2f}, frac>3 {frac3:.3f}, rms {rms:.2f}")
+    assert zmax <= 8.0 and rms <= 1.6
+
+
+def test_determinism_same_seed():
+    cfg, X, y, Xs = dataset("cfg1")
+    cfg = cfg.replace(N=2048, T=6, sweeps=3, init_sweeps=20, prec="bf16x2")
+    paths = []
+    for _ in range(2):
+        g = _gpu(cfg, X, y)
+        g.run()
+        paths.append(g.paths())
+        g.close()
+    for a, b in zip(paths[0], paths[1]):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("name,init", [("cfg3", 4), ("cfg4", 2), ("cfg3_rwm32", 4)])
+def test_full_size_sampled_parity(name, init):
+    """The live particle system at the full workload size and launch configuration:
+    sampled particles' log-likelihoods (and gradients for MALA) against the oracle."""
+    torch = _torch()
+    cfg, X, y, Xs = dataset(name)
+    g = _gpu(cfg, X, y, init_sweeps=init)
+    out = g.step()
+    assert math.isfinite(out["ess"]) and 0.0 < out["accept_rate"] < 1.0
+    beta, logw = g.particles()
+    ll = g.loglik(beta).cpu().numpy()
+    idx = np.random.default_rng(0).choice(cfg.N, size=48, replace=False)
+    b = beta[idx].double().cpu().numpy()
+    ref = likelihood.loglik(b, Xs, y)
+    e = rel_err(ll[idx], ref)
+    print(f"{name}: sampled loglik max rel err {e.max():.3e}")
+    assert e.max() <= 1e-4
+    if cfg.move == "mala":
+        gr, _ = g.grad(beta, out["lambda"])
+        gr = gr[idx].double().cpu().numpy()
+        g_ref = likelihood.grad_loglik(b, Xs, y) + gt_prior.gt_grad(b, cfg.a, out["lambda"])
+        tol = 1e-4 * np.abs(Xs).sum(axis=0) + 2.0 ** -23 * np.abs(g_ref)
+        assert np.all(np.abs(gr - g_ref) <= tol)
+    assert np.all(np.isfinite(logw.cpu().numpy()))
