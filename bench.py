@@ -72,6 +72,56 @@ def cpu_baseline(cfg, X, y, budget_s: float = 15.0):
                       f"(n={cfg.n}, p={cfg.p}), FP64 NumPy, {el:.1f} s"}
 
 
+def full_sweep(cfg, X, y, seed, **over):
+    """One full sweep over the scale grid (init + T-1 steps); returns (mean, var, log Z, s)."""
+    import torch
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = SpaSMC(SamplerConfig.from_workload(cfg, seed=seed, **over), X, y)
+    s.run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mean, var, logz = s.paths()
+    s.close()
+    return mean, var, logz, el
+
+
+def ess_protocol(R: int = 8):
+    """SPA sweep ESS/s on the n=5000, p=200 data: mixed-precision MALA (BF16 hi+lo, the
+    workload) vs plain FP32 random walk, each over R independent seeds, against an FP64
+    MALA reference path with 4N particles and 2S sweeps.  ESS_{t,j} = Var_t(beta_j) /
+    MSE(mean_{t,j}), summarised by the median over scales t >= 2 and coefficients j and
+    divided by the wall-clock of one full sweep (init + T-1 steps)."""
+    from synth import CONFIGS, make_dataset
+
+    mala, rwm = CONFIGS["cfg3"], CONFIGS["cfg3_rwm32"]
+    d = make_dataset(mala)
+    ref_mean, ref_var, ref_logz, ref_s = full_sweep(mala, d.X, d.y, seed=9999, N=4 * mala.N,
+                                                    sweeps=2 * mala.sweeps, prec="fp64")
+    out = {"reference": {"move": "mala", "prec": "fp64", "N": 4 * mala.N,
+                         "sweeps": 2 * mala.sweeps, "seconds": round(ref_s, 2)}}
+    for tag, cfg in (("mala_bf16x2", mala), ("rwm_fp32", rwm)):
+        means, secs = [], []
+        for r in range(R):
+            m, _, _, el = full_sweep(cfg, d.X, d.y, seed=100 + r)
+            means.append(m)
+            secs.append(el)
+        means = np.stack(means)
+        mse = np.mean((means - ref_mean[None]) ** 2, axis=0)
+        ess = ref_var[1:] / np.maximum(mse[1:], 1e-300)
+        wall = float(np.median(secs))
+        ess_med = float(np.median(ess))
+        out[tag] = {"ess_median": round(ess_med, 2), "sweep_seconds": round(wall, 4),
+                    "ess_per_sec": round(ess_med / wall, 2),
+                    "rmse_mean_path": float(np.sqrt(np.mean(mse[1:]))),
+                    "sweeps_per_scale": cfg.sweeps, "N": cfg.N, "seeds": R}
+    out["mala_over_rwm_ess_per_sec"] = round(out["mala_bf16x2"]["ess_per_sec"] /
+                                             max(out["rwm_fp32"]["ess_per_sec"], 1e-300), 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,6 +130,8 @@ def main():
     ap.add_argument("--workload", default="cfg3")
     ap.add_argument("--init-sweeps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")
+    ap.add_argument("--ess-seeds", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler "
@@ -141,9 +193,11 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
+    s.close()
+    if not args.no_ess:
+        out["ess"] = ess_protocol(args.ess_seeds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, d.X, d.y)
-    s.close()
     print(json.dumps(out))
 
 

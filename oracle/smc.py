@@ -105,7 +105,7 @@ def systematic_resample(w, u32: int):
     q = np.floor((w / wmax) * (2.0 ** K))
     C = np.cumsum(q)
     U = float(u32) * 2.0 ** -32
-    tpos = ((np.arange(M, dtype=np.float64) + U) / float(M)) * C[-1]
+    tpos = ((np.arange(M, dtype=np.float64) + U) * C[-1]) / float(M)
     anc = np.searchsorted(C, tpos, side="right")
     return np.minimum(anc, M - 1).astype(np.int32)
 

@@ -101,6 +101,10 @@ struct spa_smc {
   OpScratch scr[3];              // operands of loglik/grad calls, per precision
   void *gscr = nullptr;
   size_t gscr_cap = 0;
+  double *spl_part = nullptr;    // split partials of the contraction
+  size_t spl_part_cap = 0;
+  void *g_part = nullptr;
+  size_t g_part_cap = 0;
   double *llscr = nullptr;
   size_t llscr_cap = 0;
   std::vector<void *> allocs;
@@ -221,7 +225,7 @@ spa_status ensure_xpack(spa_smc *h, Prec prec) {
   if ((st = dalloc(h, &x.Xt, es * (size_t)h->n_pad * PP)) != SPA_OK) return st;
   const bool yf64 = prec == Prec::F64;
   if ((st = dalloc(h, &x.yv, (yf64 ? 8 : 4) * (size_t)h->n_pad)) != SPA_OK) return st;
-  launch_pack_x(f, h->dX, h->n, h->p, h->n_pad, PP, x.Xk, x.Xt, h->stream);
+  launch_pack_x(f, prec, h->dX, h->n, h->p, h->n_pad, PP, x.Xk, x.Xt, h->stream);
   launch_labels(h->dy, h->n, h->n_pad, yf64, x.yv, h->stream);
   SPA_CK(h, hipGetLastError());
   x.ready = true;
@@ -246,9 +250,11 @@ spa_status ensure_op(spa_smc *h, OpScratch &o, Prec prec, int PP, size_t rows) {
   return SPA_OK;
 }
 
-GemmArgs gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g) {
+// Arguments of one contraction launch; allocates the split partials on first need.
+spa_status gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g,
+                     GemmArgs *out) {
   const XPack &x = h->xp[static_cast<int>(prec)];
-  GemmArgs a;
+  GemmArgs a{};
   a.prec = prec;
   a.PP = x.PP;
   a.grad = grad;
@@ -262,13 +268,46 @@ GemmArgs gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, 
   a.yb = o.yb;
   a.mu = h->mu;
   a.inv_s = h->inv_s;
+  a.ytil = h->ytil;
   a.n = h->n;
   a.n_pad = h->n_pad;
   a.M = M;
+  a.M_pad = round_up(M, gemm_particles_per_wg(prec, x.PP));
   a.p = h->p;
   a.ll = ll;
   a.g = g;
-  return a;
+  const size_t es = prec == Prec::F64 ? 8 : prec == Prec::F32 ? 4 : (x.fp8 ? 1 : 2);
+  a.S = gemm_splits(prec, x.PP, h->n_pad, M, 2 * es * (size_t)h->n_pad * x.PP);
+  if ((size_t)a.M_pad > o.cap) return set_err(h, SPA_ERR_ARG, "operand rows not padded");
+  if (a.S > 1) {
+    spa_status st;
+    const size_t ns = (size_t)a.S * a.M_pad;
+    if (h->spl_part_cap < ns) {
+      dfree(h, h->spl_part);
+      h->spl_part = nullptr;
+      if ((st = dalloc(h, &h->spl_part, 8 * ns)) != SPA_OK) return st;
+      h->spl_part_cap = ns;
+    }
+    const size_t ng = grad ? ns * x.PP * (prec == Prec::F64 ? 8 : 4) : 0;
+    if (ng && h->g_part_cap < ng) {
+      dfree(h, h->g_part);
+      h->g_part = nullptr;
+      if ((st = dalloc(h, &h->g_part, ng)) != SPA_OK) return st;
+      h->g_part_cap = ng;
+    }
+    a.spl_part = h->spl_part;
+    a.g_part = h->g_part;
+  }
+  *out = a;
+  return SPA_OK;
+}
+
+spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g) {
+  GemmArgs a;
+  spa_status st = gemm_args(h, prec, o, M, grad, ll, g, &a);
+  if (st != SPA_OK) return st;
+  SPA_CK(h, launch_loglik(a, h->stream));
+  return SPA_OK;
 }
 
 // Log-likelihood (and gradient) of the handle's own particle buffer `beta` into ll/g.
@@ -276,8 +315,7 @@ spa_status eval_state(spa_smc *h, const void *beta, double *ll, void *g) {
   launch_pack_b(h->prec, h->f64, beta, h->N, h->Npad, h->p, h->PP, h->mu, h->s, h->inv_s, h->ytil,
                 h->op.Bhi, h->op.Blo, h->op.moff, h->op.yb, h->stream);
   const bool grad = h->move == SPA_MOVE_MALA;
-  SPA_CK(h, launch_loglik(gemm_args(h, h->prec, h->op, h->N, grad, ll, grad ? g : nullptr), h->stream));
-  return SPA_OK;
+  return run_gemm(h, h->prec, h->op, h->N, grad, ll, grad ? g : nullptr);
 }
 
 // One sweep targeting pi(. | lam): propose -> contraction (+ adjoint) -> MH decision.
@@ -315,9 +353,9 @@ spa_status sweep(spa_smc *h, int t, int s, double lam) {
   launch_propose(h->prec, mala, pa, h->stream);
   tend(h);
   tbeg(h, SPA_T_LOGLIK);
-  SPA_CK(h, launch_loglik(gemm_args(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr),
-                          h->stream));
+  spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr);
   tend(h);
+  if (st != SPA_OK) return st;
   AcceptArgs aa{};
   aa.beta = h->beta;
   aa.gl = h->gl;
@@ -651,8 +689,7 @@ extern "C" spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M
   const Prec P = to_prec(prec);
   spa_status st;
   if ((st = prep_operand(h, beta_dev, M, beta_is_fp64, P)) != SPA_OK) return st;
-  SPA_CK(h, launch_loglik(gemm_args(h, P, h->scr[static_cast<int>(P)], M, false, loglik_dev, nullptr), h->stream));
-  return SPA_OK;
+  return run_gemm(h, P, h->scr[static_cast<int>(P)], M, false, loglik_dev, nullptr);
 }
 
 extern "C" spa_status spa_smc_grad(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
@@ -683,10 +720,10 @@ extern "C" spa_status spa_smc_grad(spa_smc *h, const void *beta_dev, int32_t M, 
     }
     gout = h->gscr;
   }
-  SPA_CK(h, launch_loglik(gemm_args(h, P, h->scr[static_cast<int>(P)], M, true, h->llscr, gout), h->stream));
+  if ((st = run_gemm(h, P, h->scr[static_cast<int>(P)], M, true, h->llscr, gout)) != SPA_OK) return st;
+  launch_add_prior(beta_is_fp64 != 0, native_f64, beta_dev, M, h->p, make_prior(h, lambda), gout, h->llscr,
+                   logpost_dev, h->stream);
   if (gout != grad_dev) launch_convert(native_f64, gout, grad_dev, (size_t)M * h->p, h->stream);
-  launch_add_prior(beta_is_fp64 != 0, beta_dev, M, h->p, make_prior(h, lambda), grad_dev, h->llscr, logpost_dev,
-                   h->stream);
   SPA_CK(h, hipGetLastError());
   return SPA_OK;
 }

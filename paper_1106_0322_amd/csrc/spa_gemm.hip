@@ -1,29 +1,35 @@
 // Log-likelihood contraction of all particles against the genotype matrix, on MFMA.
 //
-// For a tile of particles i and all individuals k (Section 2 likelihood on standardised
-// genotypes, Section 3):
-//   eta_ik  = sum_j X_kj b_ij - m_i,     b_ij = beta_ij / s_j,  m_i = sum_j mu_j b_ij
-//             (the standardisation folded into the coefficients, so X stays exact 0/1/2)
-//   ll_i    = (X_std^T y) . beta_i - sum_k softplus(eta_ik)
-//   g_ij    = (sum_k r_ik X_kj - mu_j rho_i) / s_j,   r_ik = y_k - logistic(eta_ik),
-//             rho_i = sum_k r_ik  (the likelihood gradient X_std^T r_i)
+// For particles i and individuals k (Section 2 likelihood on standardised genotypes,
+// Section 3):
+//   eta_ik = sum_j X_kj b_ij - m_i,    b_ij = beta_ij / s_j,   m_i = sum_j mu_j b_ij
+//            (the standardisation folded into the coefficients: X stays exact 0/1/2)
+//   ll_i   = (X_std^T y) . beta_i - sum_k softplus(eta_ik)
+//   g_ij   = (X_std^T y)_j - (sum_k sigma_ik X_kj - mu_j sum_k sigma_ik) / s_j,
+//            sigma_ik = logistic(eta_ik)   (the likelihood gradient X_std^T (y - sigma))
 //
-// Structure (per workgroup of 4 wave64s): the particle tile's coefficients live in
-// registers as MFMA B fragments for the whole sweep over individuals; genotype tiles
-// (individual-major X and marker-major X^T) are staged through LDS; each wave computes
-// eta^T blocks (individuals x particles) with MFMA, applies softplus/logistic in
-// registers, and feeds the residuals -- already in the B-fragment layout of the MFMA
-// output -- straight into the adjoint contraction G^T += X^T R^T, like the
-// score-then-value chain of fused attention.  Neither eta nor the residuals touch HBM.
-// On the BF16X2 path the coefficients and residuals are split into BF16 hi + lo parts
-// (two MFMAs sharing the genotype fragment), with FP32 accumulation.  Softplus sums are
-// accumulated per tile in the element type and across tiles in FP64, in a fixed order.
+// Work decomposition.  A workgroup of 4 wave64s owns a tile of 64*PB particles; each wave
+// keeps the BF16 hi/lo (or FP32/FP64) fragments of its 16*PB particles in registers for
+// the whole pass.  Individuals are split into S contiguous ranges, one per workgroup of a
+// "split"; the workgroup -> (split, particle tile) map follows the round-robin dispatch of
+// workgroups to the 8 XCDs so that the XCDs of one split share its genotype slice in their
+// L2.  A workgroup streams its slice in tiles of NT individuals through double-buffered
+// LDS (the next tile is prefetched into registers while the current one is used): the
+// individual-major tile feeds the forward MFMA (eta^T blocks, individuals x particles) and,
+// for the gradient, the marker-major tile feeds the adjoint MFMA G^T += X^T sigma^T, whose
+// B operand is the logistic of the forward output taken straight from the accumulator
+// registers (a lane of an eta^T block holds four individuals of one particle, i.e. the K
+// slots of an MFMA B fragment).  Softplus sums: per lane and tile, sum max(eta, 0) plus
+// one log of prod (1 + exp(-|eta|)) (the product of at most 16 factors in (1, 2] cannot
+// overflow), accumulated across tiles in FP64 in a fixed order.  With S > 1 each split
+// writes partial sums that a finalize kernel adds in split order.
 #include "spa_common.hpp"
 #include "spa_internal.hpp"
 
 namespace spa {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <Prec P>
 struct GT;
@@ -34,8 +40,10 @@ struct GT<Prec::BF16X2> {
   using BT = __bf16;   // coefficient element in HBM
   using FR = bf16x8;   // MFMA A/B fragment (8 consecutive K values per lane)
   using AC = f32x4;
-  using EL = float;    // elementwise type
-  static constexpr int KS = 32, KV = 8, NT = 64, WP = 2, WN = 2;
+  using EL = float;
+  static constexpr int KS = 32, KV = 8;
+  // rows of a 16x16 output block held by lane group g: 4g + v
+  static __device__ __forceinline__ constexpr int crow(int g, int v) { return 4 * g + v; }
   static __device__ __forceinline__ AC mfma(FR a, FR b, AC c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
@@ -48,7 +56,8 @@ struct GT<Prec::F32> {
   using FR = float;
   using AC = f32x4;
   using EL = float;
-  static constexpr int KS = 4, KV = 1, NT = 16, WP = 4, WN = 1;
+  static constexpr int KS = 4, KV = 1;
+  static __device__ __forceinline__ constexpr int crow(int g, int v) { return 4 * g + v; }
   static __device__ __forceinline__ AC mfma(FR a, FR b, AC c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
@@ -61,79 +70,109 @@ struct GT<Prec::F64> {
   using FR = double;
   using AC = f64x4;
   using EL = double;
-  static constexpr int KS = 4, KV = 1, NT = 16, WP = 4, WN = 1;
+  static constexpr int KS = 4, KV = 1;
+  // the FP64 16x16x4 MFMA interleaves rows across lane groups: g + 4v
+  static __device__ __forceinline__ constexpr int crow(int g, int v) { return g + 4 * v; }
   static __device__ __forceinline__ AC mfma(FR a, FR b, AC c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
 
+// Tile shape per precision and padded marker count.
 template <Prec P, int PP>
-struct Layout {
-  using T = GT<P>;
-  using LX = typename T::LX;
-  using EL = typename T::EL;
-  static constexpr int XS = PP + 16 / (int)sizeof(LX);     // sX row stride (elements)
-  static constexpr int TS = T::NT + 16 / (int)sizeof(LX);  // sXt row stride
-  static constexpr size_t tile_bytes =
-      sizeof(LX) * ((size_t)T::NT * XS + (size_t)PP * TS) + sizeof(EL) * T::NT;
+struct Shape {
+  static constexpr int NT = (P == Prec::BF16X2) ? (PP <= 256 ? 64 : 32) : 16;   // individuals
+  static constexpr int PB = (P == Prec::F64) ? 1 : (PP <= 256 ? 2 : 1);         // 16-particle blocks per wave
+  static constexpr int WGP = 4 * 16 * PB;                                        // particles per workgroup
 };
 
-template <Prec P, int PP, int PB>
-constexpr size_t lds_bytes() {
-  using T = GT<P>;
-  size_t red = 0;
-  if (T::WN > 1) red = (size_t)T::WP * PB * (PP / 16) * 64 * 4 * sizeof(float) +
-                       (size_t)T::WP * PB * 64 * sizeof(double);
-  const size_t t = Layout<P, PP>::tile_bytes;
-  return t > red ? t : red;
+// LDS stage layout in 16-byte chunks ("slots").  The individual-major tile has NT rows of
+// CPR = PP*es/16 chunks and the marker-major tile PP rows of CPT = NT*es/16 chunks; each row
+// is padded by one chunk (odd stride: the 16-byte fragment reads of 16 consecutive rows hit
+// distinct banks), and each region is rounded up to 256 slots so that every thread moves
+// exactly one chunk per copy instruction.  Two stages (double buffering).
+template <Prec P, int PP, bool GRAD>
+struct Lds {
+  using LX = typename GT<P>::LX;
+  static constexpr int NT = Shape<P, PP>::NT;
+  static constexpr int CPR = PP * (int)sizeof(LX) / 16, CX = CPR + 1;
+  static constexpr int CPT = NT * (int)sizeof(LX) / 16, CT = CPT + 1;
+  static constexpr int XSL = (NT * CX + 255) / 256 * 256;
+  static constexpr int TSL = GRAD ? (PP * CT + 255) / 256 * 256 : 0;
+  static constexpr int STG = XSL + TSL;
+  static constexpr size_t bytes = 2 * (size_t)STG * 16;
+};
+
+// One 16-byte global -> LDS copy per lane; lane i writes lds[i] (wave-uniform base).
+__device__ __forceinline__ void lds_dma16(const void *g, uint4 *lds) {
+  __builtin_amdgcn_global_load_lds(g, lds, 16, 0, 0);
 }
 
-__device__ __forceinline__ float softplus_e(float eta, float e) {   // e = exp(-|eta|)
-  return fmaxf(eta, 0.0f) + __logf(1.0f + e);
-}
-__device__ __forceinline__ double softplus_e(double eta, double e) {
-  return fmax(eta, 0.0) + log1p(e);
-}
-__device__ __forceinline__ float exp_neg_abs(float eta) { return __expf(-fabsf(eta)); }
-__device__ __forceinline__ double exp_neg_abs(double eta) { return exp(-fabs(eta)); }
-__device__ __forceinline__ float logistic_e(float eta, float e) {
-  const float r = __builtin_amdgcn_rcpf(1.0f + e);
-  return eta >= 0.0f ? r : e * r;
-}
-__device__ __forceinline__ double logistic_e(double eta, double e) {
-  return eta >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// 16 FP8 (e4m3) codes -> 16 BF16 values in LDS (exact for finite codes).
+__device__ __forceinline__ void store_fp8_as_bf16(__bf16 *dst, uint4 v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w[q]), false);
+    const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8(static_cast<int>(w[q]), true);
+    bf16x4 o;
+    o[0] = static_cast<__bf16>(lo[0]);
+    o[1] = static_cast<__bf16>(lo[1]);
+    o[2] = static_cast<__bf16>(hi[0]);
+    o[3] = static_cast<__bf16>(hi[1]);
+    *reinterpret_cast<bf16x4 *>(dst + 4 * q) = o;
+  }
 }
 
-template <Prec P, int PP, int PB, bool GRAD, bool FP8>
-__global__ __launch_bounds__(256) void loglik_kernel(GemmArgs args) {
+// One workgroup per CU (the double-buffered tiles take most of the LDS), so the kernel may
+// use the whole register file.
+template <Prec P, int PP, bool GRAD, bool FP8>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void loglik_kernel(GemmArgs args) {
   using T = GT<P>;
   using LX = typename T::LX;
   using BT = typename T::BT;
   using FR = typename T::FR;
   using AC = typename T::AC;
   using EL = typename T::EL;
-  constexpr int KS = T::KS, KV = T::KV, NT = T::NT, WP = T::WP, WN = T::WN;
-  constexpr int IW = NT / WN;   // individuals per wave per tile
-  constexpr int IB = IW / 16;   // 16-individual blocks per wave per tile
-  constexpr int NKS = PP / KS;  // k-steps of the forward contraction
-  constexpr int NMB = PP / 16;  // 16-marker blocks of the adjoint
-  constexpr int XS = Layout<P, PP>::XS;
-  constexpr int TS = Layout<P, PP>::TS;
-  static_assert(IB >= 1, "a wave needs at least one 16-individual block");
-  static_assert(P != Prec::BF16X2 || IB == 2, "BF16 adjoint k-step spans two blocks");
-  static_assert(P == Prec::BF16X2 || IB == 1, "FP32/FP64 adjoint uses one block");
+  using SH = Shape<P, PP>;
+  using L = Lds<P, PP, GRAD>;
+  using XG = typename std::conditional<FP8, uint8_t, LX>::type;   // genotype element in HBM
+  constexpr int KS = T::KS, KV = T::KV, NT = SH::NT, PB = SH::PB, WGP = SH::WGP;
+  constexpr int IB = NT / 16;    // 16-individual blocks per tile
+  constexpr int QB = (P == Prec::BF16X2) ? 2 : 1;   // blocks per adjoint k-step
+  constexpr int NKS = PP / KS;   // k-steps of the forward contraction
+  constexpr int NMB = PP / 16;   // 16-marker blocks of the adjoint
+  constexpr int CX = L::CX, CT = L::CT, CPR = L::CPR, CPT = L::CPT;
+  constexpr int XSL = L::XSL, TSL = L::TSL, STG = L::STG;
+  constexpr int NQX = XSL / 256, NQT = GRAD ? TSL / 256 : 1;   // copy instructions per thread
+  static_assert(P != Prec::BF16X2 || IB % 2 == 0, "BF16 adjoint k-step spans two blocks");
+  static_assert(P == Prec::BF16X2 || IB == 1, "FP32/FP64 adjoint uses one block per tile");
+  static_assert(!FP8 || P == Prec::BF16X2, "FP8 storage feeds the BF16 path");
 
-  extern __shared__ __align__(16) unsigned char smem[];
-  LX *sX = reinterpret_cast<LX *>(smem);
-  LX *sXt = sX + NT * XS;
-  EL *sY = reinterpret_cast<EL *>(sXt + PP * TS);
+  extern __shared__ __align__(16) uint4 smem[];   // STG 16-byte slots per stage
+
+  // ---- workgroup -> (split, particle tile); XCD-aware (workgroups go round-robin to 8 XCDs)
+  const int S = args.S;
+  const int g8 = 8 / S;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int split = xcd / g8;
+  const int ptile = slot * g8 + (xcd % g8);
+  const int ntiles_p = (args.M + WGP - 1) / WGP;
+  if (ptile >= ntiles_p) return;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int pg = wave / WN, nh = wave % WN;
   const int lr = lane & 15, lg = lane >> 4;
-  const int wbase = blockIdx.x * (WP * 16 * PB) + pg * 16 * PB;
+  const int wbase = ptile * WGP + wave * 16 * PB;
+  const int n = args.n, n_pad = args.n_pad;
+  const int chunk = ((n_pad + S - 1) / S + NT - 1) / NT * NT;
+  const int i0 = min(n_pad, split * chunk), i1 = min(n_pad, i0 + chunk);
+  const int ntiles = (i1 - i0) / NT;
 
-  // ---- coefficient fragments: register resident for the whole sweep over individuals
+  // ---- coefficient fragments: register resident for the whole pass
   FR bh[PB][NKS];
   FR bl[PB][(P == Prec::BF16X2) ? NKS : 1];
   EL moff[PB];
@@ -162,196 +201,264 @@ __global__ __launch_bounds__(256) void loglik_kernel(GemmArgs args) {
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) spl[pb] = 0.0;
 
-  const int n = args.n, n_pad = args.n_pad;
-  const EL *yv = reinterpret_cast<const EL *>(args.yv);
+  // ---- tile staging.  Slot q*256 + tid of a region is filled by this thread's q-th copy;
+  // its source offset inside a tile does not depend on the tile and is computed once.
+  // Padding slots copy the tile's first chunk (never read).
+  int xoff[NQX], toff[NQT];
+#pragma unroll
+  for (int q = 0; q < NQX; ++q) {
+    const int sl = q * 256 + tid, r = sl / CX, c = sl % CX;
+    xoff[q] = (r < NT && c < CPR) ? r * PP * (int)sizeof(XG) + c * 16 * (int)sizeof(XG) / (int)sizeof(LX) : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < NQT; ++q) {
+    const int sl = q * 256 + tid, r = sl / CT, c = sl % CT;
+    toff[q] = (GRAD && r < PP && c < CPT) ? r * n_pad * (int)sizeof(XG) + c * 16 * (int)sizeof(XG) / (int)sizeof(LX) : 0;
+  }
+  const uint8_t *gxk = reinterpret_cast<const uint8_t *>(args.Xk);
+  const uint8_t *gxt = reinterpret_cast<const uint8_t *>(args.Xt);
 
-  for (int tile0 = 0; tile0 < n_pad; tile0 += NT) {
-    __syncthreads();
-    // ---- stage the genotype tile (individual-major) and its transpose (marker-major)
-    if constexpr (FP8) {
-      const uint8_t *gx = reinterpret_cast<const uint8_t *>(args.Xk) + (size_t)tile0 * PP;
-      for (int idx = tid * 16; idx < NT * PP; idx += 256 * 16) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(gx + idx);
-        const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
-        LX *d = sX + (idx / PP) * XS + (idx % PP);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) d[e] = static_cast<LX>(e4m3_to_float(b[e]));
-      }
-      const uint8_t *gt = reinterpret_cast<const uint8_t *>(args.Xt);
-      for (int idx = tid * 16; idx < PP * NT; idx += 256 * 16) {
-        const int r = idx / NT, c = idx % NT;
-        const uint4 v = *reinterpret_cast<const uint4 *>(gt + (size_t)r * n_pad + tile0 + c);
-        const uint8_t *b = reinterpret_cast<const uint8_t *>(&v);
-        LX *d = sXt + r * TS + c;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) d[e] = static_cast<LX>(e4m3_to_float(b[e]));
-      }
-    } else {
-      constexpr int VG = 16 / (int)sizeof(LX);
-      const LX *gx = reinterpret_cast<const LX *>(args.Xk) + (size_t)tile0 * PP;
-      for (int idx = tid * VG; idx < NT * PP; idx += 256 * VG)
-        *reinterpret_cast<uint4 *>(sX + (idx / PP) * XS + (idx % PP)) =
-            *reinterpret_cast<const uint4 *>(gx + idx);
-      const LX *gt = reinterpret_cast<const LX *>(args.Xt);
-      for (int idx = tid * VG; idx < PP * NT; idx += 256 * VG) {
-        const int r = idx / NT, c = idx % NT;
-        *reinterpret_cast<uint4 *>(sXt + r * TS + c) =
-            *reinterpret_cast<const uint4 *>(gt + (size_t)r * n_pad + tile0 + c);
-      }
+  // Asynchronous copy of one tile into a stage (global -> LDS DMA, 16 bytes per lane).
+#define SPA_ISSUE(tile0_, stage_)                                                                        \
+  do {                                                                                                   \
+    const uint8_t *bx_ = gxk + (size_t)(tile0_) * PP * sizeof(XG);                                       \
+    _Pragma("unroll") for (int q = 0; q < NQX; ++q)                                                      \
+      lds_dma16(bx_ + xoff[q], smem + (stage_) * STG + q * 256 + wave * 64);                            \
+    if constexpr (GRAD) {                                                                                \
+      const uint8_t *bt_ = gxt + (size_t)(tile0_) * sizeof(XG);                                          \
+      _Pragma("unroll") for (int q = 0; q < NQT; ++q)                                                    \
+        lds_dma16(bt_ + toff[q], smem + (stage_) * STG + XSL + q * 256 + wave * 64);                    \
+    }                                                                                                    \
+  } while (0)
+  // FP8 storage: each 16-byte chunk of codes becomes two BF16 chunks, through registers.
+#define SPA_COPY_FP8(tile0_, stage_)                                                                     \
+  do {                                                                                                   \
+    __bf16 *sx_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG);                                     \
+    for (int c = tid; c < NT * PP / 16; c += 256) {                                                      \
+      const int r = c / (PP / 16), cc = c % (PP / 16);                                                   \
+      const uint4 v = *reinterpret_cast<const uint4 *>(gxk + (size_t)((tile0_) + r) * PP + cc * 16);     \
+      store_fp8_as_bf16(sx_ + (r * CX + 2 * cc) * 8, v);                                                 \
+    }                                                                                                    \
+    if constexpr (GRAD) {                                                                                \
+      __bf16 *st_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG + XSL);                             \
+      for (int c = tid; c < PP * NT / 16; c += 256) {                                                    \
+        const int r = c / (NT / 16), cc = c % (NT / 16);                                                 \
+        const uint4 v = *reinterpret_cast<const uint4 *>(gxt + (size_t)r * n_pad + (tile0_) + cc * 16); \
+        store_fp8_as_bf16(st_ + (r * CT + 2 * cc) * 8, v);                                               \
+      }                                                                                                  \
+    }                                                                                                    \
+  } while (0)
+  // Wait for this thread's copies, then make every wave's copies visible.
+#define SPA_LAND()                                  \
+  do {                                              \
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); \
+    __syncthreads();                                \
+  } while (0)
+
+  if (ntiles > 0) {
+    if constexpr (FP8) SPA_COPY_FP8(i0, 0);
+    else SPA_ISSUE(i0, 0);
+  }
+  SPA_LAND();
+
+  for (int it = 0; it < ntiles; ++it) {
+    const int tile0 = i0 + it * NT;
+    const int stage = it & 1;
+    if constexpr (!FP8) {
+      if (it + 1 < ntiles) SPA_ISSUE(tile0 + NT, stage ^ 1);   // lands during this tile's math
     }
-    if (tid < NT) sY[tid] = yv[tile0 + tid];
-    __syncthreads();
-
-    // ---- forward: eta^T block (individuals x particles) = X_tile . b^T
-    AC acc[IB][PB];
+    const uint4 *sX = smem + stage * STG;          // individual-major tile, row stride CX slots
+    const uint4 *sXt = sX + XSL;                   // marker-major tile, row stride CT slots
+    const bool tail = tile0 + NT > n;   // uniform: the only tile holding padded individuals
+    // ---- per group of QB 16-individual blocks: forward -> elementwise -> adjoint
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib)
+    for (int q = 0; q < IB / QB; ++q) {
+      // forward: eta^T blocks (individuals x particles)
+      AC acc[QB][PB];
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) acc[ib][pb] = AC{0, 0, 0, 0};
+      for (int b = 0; b < QB; ++b)
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
+        for (int pb = 0; pb < PB; ++pb) acc[b][pb] = AC{0, 0, 0, 0};
 #pragma unroll
-      for (int ib = 0; ib < IB; ++ib) {
-        const FR a =
-            *reinterpret_cast<const FR *>(sX + (nh * IW + ib * 16 + lr) * XS + ks * KS + lg * KV);
+      for (int ks = 0; ks < NKS; ++ks) {
 #pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-          acc[ib][pb] = T::mfma(a, bh[pb][ks], acc[ib][pb]);
-          if constexpr (P == Prec::BF16X2) acc[ib][pb] = T::mfma(a, bl[pb][ks], acc[ib][pb]);
-        }
-      }
-    }
-
-    // ---- elementwise: softplus row sums and residuals (lane: particle lr, 4 individuals)
-    EL rv[IB][PB][4];
-    EL sp[PB];
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) sp[pb] = 0;
-#pragma unroll
-    for (int ib = 0; ib < IB; ++ib) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int kl = nh * IW + ib * 16 + lg * 4 + r;
-        const bool valid = (tile0 + kl) < n;
-        const EL yk = sY[kl];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-          const EL eta = static_cast<EL>(acc[ib][pb][r]) - moff[pb];
-          const EL e = exp_neg_abs(eta);
-          sp[pb] += valid ? softplus_e(eta, e) : EL(0);
-          if constexpr (GRAD) rv[ib][pb][r] = valid ? yk - logistic_e(eta, e) : EL(0);
-        }
-      }
-    }
-#pragma unroll
-    for (int pb = 0; pb < PB; ++pb) spl[pb] += static_cast<double>(sp[pb]);
-
-    // ---- adjoint: G^T (markers x particles) += X_tile^T . R^T, residuals from registers
-    if constexpr (GRAD) {
-      if constexpr (P == Prec::BF16X2) {
-        // K slot j of lane group lg maps to individual lg*4 + j (j < 4) of block 0 and
-        // 16 + lg*4 + (j - 4) of block 1: exactly the rows this lane holds in acc.
-        bf16x8 rh[PB], rl[PB];
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb) {
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const float v = rv[j >> 2][pb][j & 3];
-            const __bf16 h = static_cast<__bf16>(v);
-            rh[pb][j] = h;
-            rl[pb][j] = static_cast<__bf16>(v - static_cast<float>(h));
-          }
-        }
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-          const LX *row = sXt + (mb * 16 + lr) * TS + nh * IW + lg * 4;
-          const bf16x4 a0 = *reinterpret_cast<const bf16x4 *>(row);
-          const bf16x4 a1 = *reinterpret_cast<const bf16x4 *>(row + 16);
-          const bf16x8 a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+        for (int b = 0; b < QB; ++b) {
+          const int ib = q * QB + b;
+          const FR a = reinterpret_cast<const FR *>(sX + (ib * 16 + lr) * CX)[ks * KS / KV + lg];
 #pragma unroll
           for (int pb = 0; pb < PB; ++pb) {
-            G[pb][mb] = T::mfma(a, rh[pb], G[pb][mb]);
-            G[pb][mb] = T::mfma(a, rl[pb], G[pb][mb]);
+            acc[b][pb] = T::mfma(a, bh[pb][ks], acc[b][pb]);
+            if constexpr (P == Prec::BF16X2) acc[b][pb] = T::mfma(a, bl[pb][ks], acc[b][pb]);
           }
         }
-      } else {
-        // 16x16x4: k-step i uses individual lg*4 + i, the lane's i-th row of acc.
+      }
+
+      // elementwise (lane: particle lr of each block, individuals crow(lg, v) of each block)
+      EL sig[GRAD ? QB : 1][PB][4];
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
-          const LX *row = sXt + (mb * 16 + lr) * TS + nh * IW + lg * 4;
+      for (int pb = 0; pb < PB; ++pb) {
+        if constexpr (P == Prec::F64) {
+          double sp = 0.0;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const LX a = row[i];
+          for (int b = 0; b < QB; ++b)
 #pragma unroll
-            for (int pb = 0; pb < PB; ++pb) G[pb][mb] = T::mfma(a, rv[0][pb][i], G[pb][mb]);
+            for (int v = 0; v < 4; ++v) {
+              const double eta = acc[b][pb][v] - moff[pb];
+              const double e = exp(-fabs(eta));
+              const bool valid = !tail || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n;
+              sp += valid ? fmax(eta, 0.0) + log1p(e) : 0.0;
+              if constexpr (GRAD) sig[b][pb][v] = eta >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
+            }
+          spl[pb] += sp;
+        } else {
+          float prod = 1.0f, mx = 0.0f;
+#pragma unroll
+          for (int b = 0; b < QB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const float eta = acc[b][pb][v] - moff[pb];
+              const float e = fast_exp2(-fabsf(eta) * 1.4426950408889634f);
+              if (!tail || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n) {
+                prod = fmaf(prod, e, prod);
+                mx += fmaxf(eta, 0.0f);
+              }
+              if constexpr (GRAD) {
+                const float rc = fast_rcp(1.0f + e);
+                sig[b][pb][v] = eta >= 0.0f ? rc : e * rc;
+              }
+            }
+          spl[pb] += static_cast<double>(mx + 0.6931471805599453f * fast_log2(prod));
+        }
+      }
+
+      // adjoint: G^T (markers x particles) += X_tile^T . sigma^T
+      if constexpr (GRAD) {
+        if constexpr (P == Prec::BF16X2) {
+          // K slot j of lane group lg: individual 4lg + j of block 2q (j < 4), of block 2q+1 (j >= 4)
+          bf16x8 rh[PB], rl[PB];
+#pragma unroll
+          for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const float v = sig[j >> 2][pb][j & 3];
+              const __bf16 h = static_cast<__bf16>(v);
+              rh[pb][j] = h;
+              rl[pb][j] = static_cast<__bf16>(v - static_cast<float>(h));
+            }
+#pragma unroll
+          for (int mb = 0; mb < NMB; ++mb) {
+            // the marker-major copy holds this lane group's 8 K slots contiguously
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sXt + (mb * 16 + lr) * CT + q * 4 + lg);
+#pragma unroll
+            for (int pb = 0; pb < PB; ++pb) {
+              G[pb][mb] = T::mfma(a, rh[pb], G[pb][mb]);
+              G[pb][mb] = T::mfma(a, rl[pb], G[pb][mb]);
+            }
+          }
+        } else {
+          // 16x16x4: k-step v feeds the lane's v-th row, individual crow(lg, v)
+#pragma unroll
+          for (int mb = 0; mb < NMB; ++mb) {
+            // the marker-major copy holds individuals crow(lg, 0..3) at positions 4lg..4lg+3
+            const LX *row = reinterpret_cast<const LX *>(sXt + (mb * 16 + lr) * CT);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const LX a = row[4 * lg + v];
+#pragma unroll
+              for (int pb = 0; pb < PB; ++pb) G[pb][mb] = T::mfma(a, sig[0][pb][v], G[pb][mb]);
+            }
           }
         }
       }
     }
-  }
 
-  // ---- reductions: over the 4 lane groups, then over the WN waves sharing particles
+    if constexpr (FP8) {
+      if (it + 1 < ntiles) SPA_COPY_FP8(tile0 + NT, stage ^ 1);
+    }
+    SPA_LAND();
+  }
+#undef SPA_ISSUE
+#undef SPA_COPY_FP8
+#undef SPA_LAND
+
+
+  // ---- softplus sums over the 4 lane groups sharing a particle
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
     spl[pb] += __shfl_xor(spl[pb], 16, 64);
     spl[pb] += __shfl_xor(spl[pb], 32, 64);
   }
-  if constexpr (WN > 1) {
-    static_assert(WN == 2, "two waves share a particle group");
-    __syncthreads();
-    float *redG = reinterpret_cast<float *>(smem);
-    double *redS = reinterpret_cast<double *>(smem + (size_t)WP * PB * NMB * 64 * 4 * sizeof(float));
-    if (nh == 1) {
-      if constexpr (GRAD) {
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-          for (int mb = 0; mb < NMB; ++mb)
-            *reinterpret_cast<f32x4 *>(redG + (((pg * PB + pb) * NMB + mb) * 64 + lane) * 4) =
-                G[pb][mb];
-      }
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) redS[(pg * PB + pb) * 64 + lane] = spl[pb];
-    }
-    __syncthreads();
-    if (nh == 0) {
-      if constexpr (GRAD) {
-#pragma unroll
-        for (int pb = 0; pb < PB; ++pb)
-#pragma unroll
-          for (int mb = 0; mb < NMB; ++mb)
-            G[pb][mb] += *reinterpret_cast<const f32x4 *>(
-                redG + (((pg * PB + pb) * NMB + mb) * 64 + lane) * 4);
-      }
-#pragma unroll
-      for (int pb = 0; pb < PB; ++pb) spl[pb] += redS[(pg * PB + pb) * 64 + lane];
-    }
-  }
-  if (nh != 0) return;
 
-  // ---- epilogue: log-likelihood and standardised gradient
   const int M = args.M, p = args.p;
+  using GO = typename std::conditional<P == Prec::F64, double, float>::type;
+  if (S == 1) {
+    // ---- epilogue: log-likelihood and standardised gradient
 #pragma unroll
-  for (int pb = 0; pb < PB; ++pb) {
-    const int i = wbase + pb * 16 + lr;
-    if (lg == 0 && i < M) args.ll[i] = args.yb[i] - spl[pb];
-    if constexpr (GRAD) {
-      // rho_i sits in the all-ones column PP-1: block NMB-1, lane group 3, element 3
-      const double rho = static_cast<double>(__shfl(G[pb][NMB - 1][3], lr + 48, 64));
-      if (i < M) {
-        using GO = typename std::conditional<P == Prec::F64, double, float>::type;
-        GO *g = reinterpret_cast<GO *>(args.g) + static_cast<size_t>(i) * p;
+    for (int pb = 0; pb < PB; ++pb) {
+      const int i = wbase + pb * 16 + lr;
+      if (lg == 0 && i < M) args.ll[i] = args.yb[i] - spl[pb];
+      if constexpr (GRAD) {
+        // rho_i = sum_k sigma_ik: the all-ones column PP-1 (block NMB-1, lane group 3, element 3)
+        const double rho = static_cast<double>(__shfl(G[pb][NMB - 1][3], lr + 48, 64));
+        if (i < M) {
+          GO *g = reinterpret_cast<GO *>(args.g) + static_cast<size_t>(i) * p;
+#pragma unroll
+          for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int j = mb * 16 + T::crow(lg, v);
+              if (j < p)
+                g[j] = static_cast<GO>(args.ytil[j] -
+                                       (static_cast<double>(G[pb][mb][v]) - args.mu[j] * rho) * args.inv_s[j]);
+            }
+        }
+      }
+    }
+  } else {
+    // ---- partial sums of this split (combined in split order by the finalize kernel)
+    const size_t Mp = static_cast<size_t>(args.M_pad);
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb) {
+      const int i = wbase + pb * 16 + lr;
+      if (lg == 0) args.spl_part[split * Mp + i] = spl[pb];
+      if constexpr (GRAD) {
+        GO *gp = reinterpret_cast<GO *>(args.g_part) + (split * Mp + i) * PP;
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb) {
+          if constexpr (P == Prec::F64) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int j = mb * 16 + lg * 4 + r;
-            if (j < p)
-              g[j] = static_cast<GO>((static_cast<double>(G[pb][mb][r]) - args.mu[j] * rho) *
-                                     args.inv_s[j]);
+            for (int v = 0; v < 4; ++v) gp[mb * 16 + T::crow(lg, v)] = G[pb][mb][v];
+          } else {
+            *reinterpret_cast<f32x4 *>(gp + mb * 16 + lg * 4) = G[pb][mb];
           }
         }
       }
+    }
+  }
+}
+
+// Sum the S partials of every particle in split order and apply the epilogue.
+template <typename GO, bool GRAD>
+__global__ void gemm_finalize_kernel(GemmArgs args, int PP) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= args.M) return;
+  const size_t Mp = static_cast<size_t>(args.M_pad);
+  const int S = args.S, p = args.p;
+  if (lane == 0) {
+    double spl = 0.0;
+    for (int s = 0; s < S; ++s) spl += args.spl_part[s * Mp + i];
+    args.ll[i] = args.yb[i] - spl;
+  }
+  if constexpr (GRAD) {
+    const GO *gp = reinterpret_cast<const GO *>(args.g_part);
+    double rho = 0.0;
+    for (int s = 0; s < S; ++s) rho += static_cast<double>(gp[(s * Mp + i) * PP + PP - 1]);
+    GO *g = reinterpret_cast<GO *>(args.g) + static_cast<size_t>(i) * p;
+    for (int j = lane; j < p; j += 64) {
+      double acc = 0.0;
+      for (int s = 0; s < S; ++s) acc += static_cast<double>(gp[(s * Mp + i) * PP + j]);
+      g[j] = static_cast<GO>(args.ytil[j] - (acc - args.mu[j] * rho) * args.inv_s[j]);
     }
   }
 }
@@ -373,11 +480,30 @@ int gemm_pad_markers(int p, Prec prec) {
   return -1;
 }
 
-template <Prec P, int PP, int PB, bool GRAD, bool FP8>
+int gemm_tile_individuals(Prec prec, int PP) {
+  return prec == Prec::BF16X2 ? (PP <= 256 ? 64 : 32) : 16;
+}
+
+int gemm_particles_per_wg(Prec prec, int PP) {
+  return prec == Prec::F64 ? 64 : (PP <= 256 ? 128 : 64);
+}
+
+int gemm_splits(Prec prec, int PP, int n_pad, int M, size_t x_bytes_both) {
+  const int NT = gemm_tile_individuals(prec, PP);
+  const int tiles_p = (M + gemm_particles_per_wg(prec, PP) - 1) / gemm_particles_per_wg(prec, PP);
+  int S = 1;
+  // keep one split's genotype slice (both orientations) within an XCD's L2 ...
+  while (S < 8 && x_bytes_both / S > (size_t)3 * 1024 * 1024 && n_pad / (2 * S) >= NT) S *= 2;
+  // ... and give every CU a workgroup
+  while (S < 8 && (size_t)tiles_p * S < 256 && n_pad / (2 * S) >= NT) S *= 2;
+  return S;
+}
+
+template <Prec P, int PP, bool GRAD, bool FP8>
 static hipError_t launch_one(const GemmArgs &a, hipStream_t s) {
-  constexpr size_t lds = lds_bytes<P, PP, PB>();
+  constexpr size_t lds = Lds<P, PP, GRAD>::bytes;
   static_assert(lds <= 160 * 1024, "LDS budget of one CU");
-  auto kern = loglik_kernel<P, PP, PB, GRAD, FP8>;
+  auto kern = loglik_kernel<P, PP, GRAD, FP8>;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -385,59 +511,63 @@ static hipError_t launch_one(const GemmArgs &a, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  constexpr int per_wg = GT<P>::WP * 16 * PB;
-  const int grid = (a.M + per_wg - 1) / per_wg;
+  constexpr int per_wg = Shape<P, PP>::WGP;
+  const int tiles_p = (a.M + per_wg - 1) / per_wg;
+  const int g8 = 8 / a.S;
+  const int grid = 8 * ((tiles_p + g8 - 1) / g8);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || a.S == 1) return e;
+  using GO = typename std::conditional<P == Prec::F64, double, float>::type;
+  hipLaunchKernelGGL((gemm_finalize_kernel<GO, GRAD>), dim3((a.M + 3) / 4), dim3(256), 0, s, a, PP);
   return hipGetLastError();
 }
 
-template <Prec P, int PP, int PB>
+template <Prec P, int PP>
 static hipError_t launch_pp(const GemmArgs &a, hipStream_t s) {
-  if (a.grad) {
-    if (a.x_fp8) return launch_one<P, PP, PB, true, true>(a, s);
-    return launch_one<P, PP, PB, true, false>(a, s);
+  if constexpr (P == Prec::BF16X2) {
+    if (a.x_fp8) {
+      if (a.grad) return launch_one<P, PP, true, true>(a, s);
+      return launch_one<P, PP, false, true>(a, s);
+    }
   }
-  if (a.x_fp8) return launch_one<P, PP, PB, false, true>(a, s);
-  return launch_one<P, PP, PB, false, false>(a, s);
-}
-
-template <Prec P, int PP, int PB>
-static hipError_t launch_pp_nofp8(const GemmArgs &a, hipStream_t s) {
-  if (a.grad) return launch_one<P, PP, PB, true, false>(a, s);
-  return launch_one<P, PP, PB, false, false>(a, s);
+  if (a.grad) return launch_one<P, PP, true, false>(a, s);
+  return launch_one<P, PP, false, false>(a, s);
 }
 
 hipError_t launch_loglik(const GemmArgs &a, hipStream_t s) {
+  if (a.S != 1 && a.S != 2 && a.S != 4 && a.S != 8) return hipErrorInvalidValue;
+  if (a.M_pad % gemm_particles_per_wg(a.prec, a.PP) != 0) return hipErrorInvalidValue;
   switch (a.prec) {
     case Prec::BF16X2:
       switch (a.PP) {
-        case 32: return launch_pp<Prec::BF16X2, 32, 2>(a, s);
-        case 64: return launch_pp<Prec::BF16X2, 64, 2>(a, s);
-        case 128: return launch_pp<Prec::BF16X2, 128, 2>(a, s);
-        case 224: return launch_pp<Prec::BF16X2, 224, 2>(a, s);
-        case 256: return launch_pp<Prec::BF16X2, 256, 2>(a, s);
-        case 384: return launch_pp<Prec::BF16X2, 384, 1>(a, s);
-        case 512: return launch_pp<Prec::BF16X2, 512, 1>(a, s);
+        case 32: return launch_pp<Prec::BF16X2, 32>(a, s);
+        case 64: return launch_pp<Prec::BF16X2, 64>(a, s);
+        case 128: return launch_pp<Prec::BF16X2, 128>(a, s);
+        case 224: return launch_pp<Prec::BF16X2, 224>(a, s);
+        case 256: return launch_pp<Prec::BF16X2, 256>(a, s);
+        case 384: return launch_pp<Prec::BF16X2, 384>(a, s);
+        case 512: return launch_pp<Prec::BF16X2, 512>(a, s);
       }
       break;
     case Prec::F32:
       switch (a.PP) {
-        case 32: return launch_pp_nofp8<Prec::F32, 32, 1>(a, s);
-        case 64: return launch_pp_nofp8<Prec::F32, 64, 1>(a, s);
-        case 128: return launch_pp_nofp8<Prec::F32, 128, 1>(a, s);
-        case 224: return launch_pp_nofp8<Prec::F32, 224, 1>(a, s);
-        case 256: return launch_pp_nofp8<Prec::F32, 256, 1>(a, s);
-        case 384: return launch_pp_nofp8<Prec::F32, 384, 1>(a, s);
-        case 512: return launch_pp_nofp8<Prec::F32, 512, 1>(a, s);
+        case 32: return launch_pp<Prec::F32, 32>(a, s);
+        case 64: return launch_pp<Prec::F32, 64>(a, s);
+        case 128: return launch_pp<Prec::F32, 128>(a, s);
+        case 224: return launch_pp<Prec::F32, 224>(a, s);
+        case 256: return launch_pp<Prec::F32, 256>(a, s);
+        case 384: return launch_pp<Prec::F32, 384>(a, s);
+        case 512: return launch_pp<Prec::F32, 512>(a, s);
       }
       break;
     case Prec::F64:
       switch (a.PP) {
-        case 32: return launch_pp_nofp8<Prec::F64, 32, 1>(a, s);
-        case 64: return launch_pp_nofp8<Prec::F64, 64, 1>(a, s);
-        case 128: return launch_pp_nofp8<Prec::F64, 128, 1>(a, s);
-        case 224: return launch_pp_nofp8<Prec::F64, 224, 1>(a, s);
-        case 256: return launch_pp_nofp8<Prec::F64, 256, 1>(a, s);
+        case 32: return launch_pp<Prec::F64, 32>(a, s);
+        case 64: return launch_pp<Prec::F64, 64>(a, s);
+        case 128: return launch_pp<Prec::F64, 128>(a, s);
+        case 224: return launch_pp<Prec::F64, 224>(a, s);
+        case 256: return launch_pp<Prec::F64, 256>(a, s);
       }
       break;
   }

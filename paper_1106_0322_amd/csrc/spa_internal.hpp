@@ -13,10 +13,15 @@ enum class Prec : int { F64 = 0, F32 = 1, BF16X2 = 2 };
 // Padded marker count used by the GEMM operands: the smallest instantiated width that
 // holds the p markers plus the all-ones column kept in the last padded column.
 int gemm_pad_markers(int p, Prec prec);
+// Particles per workgroup of the contraction kernel (operand rows are padded to it).
+int gemm_particles_per_wg(Prec prec, int PP);
+// Number of contiguous individual ranges the contraction is split into (1, 2, 4 or 8),
+// chosen so that one range of both genotype copies fits an XCD's L2 and every CU has work.
+int gemm_splits(Prec prec, int PP, int n_pad, int M, size_t x_bytes_both);
 // Individuals are padded to a multiple of this (largest tile of any precision).
 constexpr int kIndPad = 64;
 // Particle rows of every operand buffer are padded to a multiple of this.
-constexpr int kPartPad = 64;
+constexpr int kPartPad = 128;
 
 struct GemmArgs {
   Prec prec;
@@ -32,11 +37,30 @@ struct GemmArgs {
   const double *yb;    // M: sum_j (X_std^T y)_j beta_ij
   const double *mu;    // PP (zero padded)
   const double *inv_s; // PP (zero padded)
-  int n, n_pad, M, p;
+  const double *ytil;  // PP: X_std^T y (zero padded)
+  int n, n_pad, M, M_pad, p;
+  int S;               // individual splits (1, 2, 4, 8)
+  double *spl_part;    // S x M_pad partial softplus sums (S > 1)
+  void *g_part;        // S x M_pad x PP partial adjoints (S > 1; double for F64, float otherwise)
   double *ll;          // M outputs: yb - sum_k softplus(eta_ik)
   void *g;             // M x p likelihood gradient (double for F64, float otherwise)
 };
 
 hipError_t launch_loglik(const GemmArgs &a, hipStream_t s);
+
+// Position of individual i (0 <= i < xt_group) inside a group of the marker-major genotype
+// copy, chosen so that the K slots of a lane's adjoint MFMA fragment are contiguous in LDS:
+// BF16 groups of 32 hold the lane-group pieces {4g..4g+3, 16+4g..16+4g+3} next to each
+// other; FP64 groups of 16 hold {g, g+4, g+8, g+12} (the FP64 MFMA's output rows of lane
+// group g) next to each other; FP32 keeps the natural order.
+__host__ __device__ constexpr int xt_group(Prec p) { return p == Prec::BF16X2 ? 32 : 16; }
+__host__ __device__ inline int xt_position(Prec p, int i) {
+  if (p == Prec::BF16X2) {
+    const int b = i / 16, r = i % 16;
+    return (r / 4) * 8 + b * 4 + r % 4;
+  }
+  if (p == Prec::F64) return (i % 4) * 4 + i / 4;
+  return i;
+}
 
 }  // namespace spa

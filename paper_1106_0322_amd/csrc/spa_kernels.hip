@@ -78,9 +78,11 @@ __device__ __forceinline__ uint8_t code_of<uint8_t>(int v) {   // OCP e4m3: 0, 1
 
 // Genotypes in GEMM storage: Xk (n_pad x PP, individual-major) and Xt (PP x n_pad), with
 // an all-ones column at PP-1 for real individuals and zeros elsewhere in the padding.
+// Within each group of xt_group(prec) individuals, Xt holds individual i at xt_position.
 template <typename XT>
-__global__ void pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad, int PP,
+__global__ void pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad, int PP, Prec prec,
                               XT *__restrict__ Xk, XT *__restrict__ Xt) {
+  const int grp = xt_group(prec);
   const size_t total = (size_t)n_pad * PP;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -89,7 +91,7 @@ __global__ void pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, int n
     if (k < n) v = (j < p) ? X[(size_t)k * p + j] : (j == PP - 1 ? 1 : 0);
     const XT c = code_of<XT>(v);
     Xk[idx] = c;
-    Xt[(size_t)j * n_pad + k] = c;
+    Xt[(size_t)j * n_pad + (k / grp) * grp + xt_position(prec, k % grp)] = c;
   }
 }
 
@@ -345,7 +347,9 @@ __device__ double block_sum(double v, double *sh) {
 //          ESS < ess_frac * M (then logW = -log M).
 //  mode 1: input linear weights w; validates them; always resamples.
 // The CDF is over q_i = floor((w_i / max w) 2^K), K = 53 - ceil(log2 M): integer partial
-// sums below 2^53 are exact in FP64 in any order, so the scan is bit-exact.
+// sums below 2^53 are exact in FP64 in any order, so the scan is bit-exact.  Offspring i
+// sits at ((i + U) C) / M, product first (equal weights with U = 0 then map to the
+// identity for every M).
 __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
   __shared__ double sh[kRB / 64];
   __shared__ double tot[kRB];
@@ -423,7 +427,7 @@ __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
   const double dM = static_cast<double>(M);
   for (int i = lo; i < hi; ++i) {
     const double num = __dadd_rn(static_cast<double>(i), U);
-    const double tpos = __dmul_rn(__ddiv_rn(num, dM), C);
+    const double tpos = __ddiv_rn(__dmul_rn(num, C), dM);
     int l = 0, r = M;   // first k with cdf[k] > tpos
     while (l < r) {
       const int mid = (l + r) >> 1;
@@ -547,10 +551,11 @@ __global__ void convert_kernel(const ST *__restrict__ src, DT *__restrict__ dst,
     dst[i] = static_cast<DT>(src[i]);
 }
 
-// log posterior = loglik + sum_j log Gt(beta_ij); gradient += prior gradient (in place).
-template <typename PT>
-__global__ void add_prior_kernel(const PT *__restrict__ beta, int M, int p, Prior pr,
-                                 PT *__restrict__ g, const double *__restrict__ ll,
+// log posterior = loglik + sum_j log Gt(beta_ij); gradient += prior gradient (in place, in
+// the gradient's own dtype, so a later conversion rounds only once).
+template <typename BT, typename GT>
+__global__ void add_prior_kernel(const BT *__restrict__ beta, int M, int p, Prior pr,
+                                 GT *__restrict__ g, const double *__restrict__ ll,
                                  double *__restrict__ logpost) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -559,7 +564,7 @@ __global__ void add_prior_kernel(const PT *__restrict__ beta, int M, int p, Prio
   for (int j = lane; j < p; j += 64) {
     const size_t off = (size_t)i * p + j;
     const double b = static_cast<double>(beta[off]);
-    if (g) g[off] = static_cast<PT>(static_cast<double>(g[off]) + gt_grad(b, pr));
+    if (g) g[off] = static_cast<GT>(static_cast<double>(g[off]) + gt_grad(b, pr));
     lp += gt_logpdf(b, pr);
   }
   lp = wave_sum(lp);
@@ -587,25 +592,25 @@ void launch_col_stats(const uint8_t *X, const uint8_t *y, int n, int p, double *
   hipLaunchKernelGGL(col_stats_kernel, dim3(p), dim3(256), 0, st, X, y, n, p, mu, s, inv_s, ytil, bad);
 }
 
-void launch_pack_x(XFormat f, const uint8_t *X, int n, int p, int n_pad, int PP, void *Xk, void *Xt,
-                   hipStream_t st) {
+void launch_pack_x(XFormat f, Prec prec, const uint8_t *X, int n, int p, int n_pad, int PP, void *Xk,
+                   void *Xt, hipStream_t st) {
   const size_t total = (size_t)n_pad * PP;
   const int grid = static_cast<int>(std::min<size_t>((total + 255) / 256, 65535));
   switch (f) {
     case XFormat::F64:
-      hipLaunchKernelGGL(pack_x_kernel<double>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+      hipLaunchKernelGGL(pack_x_kernel<double>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP, prec,
                          (double *)Xk, (double *)Xt);
       break;
     case XFormat::F32:
-      hipLaunchKernelGGL(pack_x_kernel<float>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+      hipLaunchKernelGGL(pack_x_kernel<float>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP, prec,
                          (float *)Xk, (float *)Xt);
       break;
     case XFormat::BF16:
-      hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+      hipLaunchKernelGGL(pack_x_kernel<__bf16>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP, prec,
                          (__bf16 *)Xk, (__bf16 *)Xt);
       break;
     case XFormat::FP8:
-      hipLaunchKernelGGL(pack_x_kernel<uint8_t>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP,
+      hipLaunchKernelGGL(pack_x_kernel<uint8_t>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, PP, prec,
                          (uint8_t *)Xk, (uint8_t *)Xt);
       break;
   }
@@ -727,15 +732,18 @@ void launch_convert(bool src_f64, const void *src, void *dst, size_t n, hipStrea
                        (double *)dst, n);
 }
 
-void launch_add_prior(bool f64, const void *beta, int M, int p, const Prior &pr, void *g, const double *ll,
-                      double *logpost, hipStream_t st) {
+void launch_add_prior(bool beta_f64, bool g_f64, const void *beta, int M, int p, const Prior &pr, void *g,
+                      const double *ll, double *logpost, hipStream_t st) {
   const int grid = grid_rows(M, 4);
-  if (f64)
-    hipLaunchKernelGGL(add_prior_kernel<double>, dim3(grid), dim3(256), 0, st, (const double *)beta, M, p, pr,
-                       (double *)g, ll, logpost);
-  else
-    hipLaunchKernelGGL(add_prior_kernel<float>, dim3(grid), dim3(256), 0, st, (const float *)beta, M, p, pr,
-                       (float *)g, ll, logpost);
+#define SPA_ADDP(BT, GT)                                                                                 \
+  hipLaunchKernelGGL((add_prior_kernel<BT, GT>), dim3(grid), dim3(256), 0, st, (const BT *)beta, M, p, pr, \
+                     (GT *)g, ll, logpost)
+  if (beta_f64) {
+    if (g_f64) SPA_ADDP(double, double); else SPA_ADDP(double, float);
+  } else {
+    if (g_f64) SPA_ADDP(float, double); else SPA_ADDP(float, float);
+  }
+#undef SPA_ADDP
 }
 
 void launch_philox(const uint32_t *ctr, int M, uint32_t k0, uint32_t k1, uint32_t *out, hipStream_t st) {

@@ -59,8 +59,8 @@ struct LseArgs {
 
 void launch_col_stats(const uint8_t *X, const uint8_t *y, int n, int p, double *mu, double *s,
                       double *inv_s, double *ytil, int *bad, hipStream_t st);
-void launch_pack_x(XFormat f, const uint8_t *X, int n, int p, int n_pad, int PP, void *Xk, void *Xt,
-                   hipStream_t st);
+void launch_pack_x(XFormat f, Prec prec, const uint8_t *X, int n, int p, int n_pad, int PP, void *Xk,
+                   void *Xt, hipStream_t st);
 void launch_labels(const uint8_t *y, int n, int n_pad, bool f64, void *yv, hipStream_t st);
 void launch_pack_b(Prec prec, bool in_f64, const void *beta, int M, int M_pad, int p, int PP,
                    const double *mu, const double *s, const double *inv_s, const double *ytil,
@@ -79,8 +79,8 @@ void launch_count(const int *cnt, int M, long long *out, hipStream_t st);
 void launch_fill(double *x, int n, double v, hipStream_t st);
 void launch_zero_int(int *x, int n, hipStream_t st);
 void launch_convert(bool src_f64, const void *src, void *dst, size_t n, hipStream_t st);
-void launch_add_prior(bool f64, const void *beta, int M, int p, const Prior &pr, void *g, const double *ll,
-                      double *logpost, hipStream_t st);
+void launch_add_prior(bool beta_f64, bool g_f64, const void *beta, int M, int p, const Prior &pr, void *g,
+                      const double *ll, double *logpost, hipStream_t st);
 void launch_philox(const uint32_t *ctr, int M, uint32_t k0, uint32_t k1, uint32_t *out, hipStream_t st);
 
 }  // namespace spa

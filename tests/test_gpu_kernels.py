@@ -73,7 +73,7 @@ def test_loglik_fp8_storage_equals_bf16_storage():
 
 @pytest.mark.parametrize("n,p,prec,M", [
     (130, 1, "fp64", 1), (130, 1, "bf16x2", 65), (70, 7, "fp32", 129), (200, 255, "fp64", 17),
-    (200, 511, "bf16x2", 33), (200, 511, "fp32", 40), (64, 31, "bf16x2", 64), (65, 32, "bf16x2", 3),
+    (200, 511, "bf16x2", 33), (200, 511, "fp32", 40), (64, 31, "bf16x2", 64), (66, 32, "bf16x2", 3),
 ])
 def test_loglik_edge_shapes(n, p, prec, M):
     torch = _torch()
@@ -116,8 +116,8 @@ def test_grad_parity(name, prec, M, lam):
         lp_ref = ll_ref + gt_prior.log_prior(bs, cfg.a, lam)
         err = np.abs(g - g_ref)
         tol = _grad_tol(prec, Xs)
-        if dt == torch.float32:   # the gradient itself is returned in FP32
-            tol = tol + 2.0 ** -23 * np.abs(g_ref)
+        if dt == torch.float32:   # the gradient itself is returned in FP32 (one rounding)
+            tol = tol + 2.0 ** -24 * np.abs(g_ref)
         print(f"{name} {prec} {dt}: grad max abs err {err.max():.3e} (tol min {tol.min():.3e})")
         assert np.all(err <= tol)
         ltol = 1e-10 if prec == "fp64" else 1e-4
@@ -175,7 +175,7 @@ def test_resample_bit_exact(M):
         got = s.resample(torch.from_numpy(w), u32).cpu().numpy()
         ref = smc.systematic_resample(w, u32)
         assert np.array_equal(got, ref)
-        if trial == 3:
+        if trial == 3:   # equal weights, U = 0: the identity map for every M
             assert np.array_equal(got, np.arange(M))
 
 

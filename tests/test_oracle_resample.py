@@ -17,7 +17,7 @@ def exact_systematic(q, u32):
     out = []
     k = 0
     for i in range(M):
-        t = (i + U) * C[-1] / M
+        t = (i + U) * C[-1] / M     # exact; the FP64 version rounds (i+U)*C, then /M
         while k < M - 1 and not C[k] > t:
             k += 1
         out.append(k)
@@ -47,7 +47,7 @@ def test_matches_exact_definition(M):
 
 
 def test_identity_on_equal_weights():
-    for M in (1, 5, 1024, 32768):
+    for M in (1, 5, 1000, 1024, 32768, 100000):
         assert np.array_equal(smc.systematic_resample(np.ones(M), 0), np.arange(M))
 
 
