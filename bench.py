@@ -29,6 +29,31 @@ if ROOT not in sys.path:
 
 PEAK = {"bf16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}     # dense MFMA TFLOP/s of MI355X
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1106_0322_amd/csrc/spa_gemm.hip", "paper_1106_0322_amd/csrc/spa_common.hpp",
+                  "paper_1106_0322_amd/csrc/spa_internal.hpp"]
+TRAFFIC_PROFILE = {"cfg3": "profiles/loglik_kernel_n5000_p200_N16384_mala_bf16x2_traffic.txt"}
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch of the contraction kernel from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None when there is none for this workload or
+    the kernel source has changed since it was taken."""
+    import hashlib
+    path = TRAFFIC_PROFILE.get(workload)
+    if path is None or not os.path.exists(os.path.join(ROOT, path)):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    kv = {}
+    for line in open(os.path.join(ROOT, path)):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v
+    if kv.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    return int(kv["hbm_bytes_per_launch"])
 
 
 def gemm_flops(cfg) -> float:
@@ -187,7 +212,8 @@ def main():
                    "n": cfg.n, "p": cfg.p, "N": cfg.N, "sweeps_per_step": cfg.sweeps,
                    "move": cfg.move, "prec": cfg.prec},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": profiled_traffic(args.workload),
                      "kernel": "loglik_kernel (fused log-likelihood + adjoint)" if cfg.move == "mala"
                      else "loglik_kernel", "avg_launch_us": round(gemm_avg_ms * 1e3, 2)},
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},

@@ -196,7 +196,8 @@ spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uin
  * Kernel timing.  spa_smc_set_timing(h, 1) resets the counters and brackets every
  * subsequent launch of spa_smc_step (and of the burn-in) with HIP events on the handle's
  * stream; spa_smc_get_timing fills ms[c] (total milliseconds) and launches[c] for the
- * SPA_TIMING_CLASSES classes below.  Timing adds a few microseconds of event records per
+ * SPA_TIMING_CLASSES classes below (launches of the burn-in, spa_smc_step,
+ * spa_smc_loglik and spa_smc_grad).  Timing adds a few microseconds of event records per
  * launch; it is off by default.  Errors: SPA_ERR_ARG (null pointers).
  */
 enum {
@@ -207,7 +208,8 @@ enum {
   SPA_T_LSE = 4,        /* logsumexp / ESS / systematic resampling                     */
   SPA_T_GATHER = 5,     /* particle gather after resampling                            */
   SPA_T_MOMENTS = 6,    /* weighted moments                                            */
-  SPA_TIMING_CLASSES = 7
+  SPA_T_FINALIZE = 7,   /* ordered sum of the contraction's split partials             */
+  SPA_TIMING_CLASSES = 8
 };
 spa_status spa_smc_set_timing(spa_smc *h, int32_t enable);
 spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches);

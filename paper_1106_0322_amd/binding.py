@@ -29,7 +29,8 @@ MOVE = {"rwm": 0, "mala": 1}
 EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "spa_smc_resample",
            "spa_smc_get", "spa_smc_get_stats", "spa_smc_set_state", "spa_philox4x32_10",
            "spa_smc_set_timing", "spa_smc_get_timing", "spa_smc_destroy", "spa_smc_last_error"]
-TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments"]
+TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments",
+                  "finalize"]
 
 
 class SpaError(RuntimeError):

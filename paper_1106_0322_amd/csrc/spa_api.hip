@@ -306,7 +306,14 @@ spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad,
   GemmArgs a;
   spa_status st = gemm_args(h, prec, o, M, grad, ll, g, &a);
   if (st != SPA_OK) return st;
+  tbeg(h, SPA_T_LOGLIK);
   SPA_CK(h, launch_loglik(a, h->stream));
+  tend(h);
+  if (a.S > 1) {
+    tbeg(h, SPA_T_FINALIZE);
+    SPA_CK(h, launch_gemm_finalize(a, h->stream));
+    tend(h);
+  }
   return SPA_OK;
 }
 
@@ -352,9 +359,7 @@ spa_status sweep(spa_smc *h, int t, int s, double lam) {
   tbeg(h, SPA_T_PROPOSE);
   launch_propose(h->prec, mala, pa, h->stream);
   tend(h);
-  tbeg(h, SPA_T_LOGLIK);
   spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr);
-  tend(h);
   if (st != SPA_OK) return st;
   AcceptArgs aa{};
   aa.beta = h->beta;

@@ -105,6 +105,20 @@ __device__ __forceinline__ double gt_grad(double b, const Prior &pr) {
   return -(pr.a + 1.0) * sg / (pr.a * pr.lam + fabs(b));
 }
 
+// Precision-generic pieces of the prior, for products of a few factors (one log per lane
+// instead of one per coefficient): log Gt(b) = -log(2c) - (a+1) log(1 + |b|/(a c)).
+template <typename T>
+__device__ __forceinline__ T gt_factor(T b, T inv_ac) { return T(1) + fabs(b) * inv_ac; }
+// d/db log Gt(b) = -(a+1) sign(b) / (a c + |b|); -sign(b)/c for the double exponential.
+template <typename T>
+__device__ __forceinline__ T gt_grad_t(T b, T a1, T ac, int inf, T inv_c) {
+  const T sg = (b > T(0)) ? T(1) : ((b < T(0)) ? T(-1) : T(0));
+  if (inf) return -sg * inv_c;
+  return -a1 * sg / (ac + fabs(b));
+}
+__device__ __forceinline__ float fast_log(float x) { return __logf(x); }
+__device__ __forceinline__ double fast_log(double x) { return log(x); }
+
 // FP8 (OCP e4m3) -> float for finite normal/zero codes (the genotype codes 0/1/2 and 1
 // of the ones column are all exact).
 __device__ __forceinline__ float e4m3_to_float(uint8_t v) {

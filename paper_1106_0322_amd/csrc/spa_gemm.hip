@@ -516,10 +516,6 @@ static hipError_t launch_one(const GemmArgs &a, hipStream_t s) {
   const int g8 = 8 / a.S;
   const int grid = 8 * ((tiles_p + g8 - 1) / g8);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || a.S == 1) return e;
-  using GO = typename std::conditional<P == Prec::F64, double, float>::type;
-  hipLaunchKernelGGL((gemm_finalize_kernel<GO, GRAD>), dim3((a.M + 3) / 4), dim3(256), 0, s, a, PP);
   return hipGetLastError();
 }
 
@@ -533,6 +529,19 @@ static hipError_t launch_pp(const GemmArgs &a, hipStream_t s) {
   }
   if (a.grad) return launch_one<P, PP, true, false>(a, s);
   return launch_one<P, PP, false, false>(a, s);
+}
+
+hipError_t launch_gemm_finalize(const GemmArgs &a, hipStream_t s) {
+  if (a.S == 1) return hipSuccess;
+  const int grid = (a.M + 3) / 4;
+  if (a.prec == Prec::F64) {
+    if (a.grad) hipLaunchKernelGGL((gemm_finalize_kernel<double, true>), dim3(grid), dim3(256), 0, s, a, a.PP);
+    else hipLaunchKernelGGL((gemm_finalize_kernel<double, false>), dim3(grid), dim3(256), 0, s, a, a.PP);
+  } else {
+    if (a.grad) hipLaunchKernelGGL((gemm_finalize_kernel<float, true>), dim3(grid), dim3(256), 0, s, a, a.PP);
+    else hipLaunchKernelGGL((gemm_finalize_kernel<float, false>), dim3(grid), dim3(256), 0, s, a, a.PP);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_loglik(const GemmArgs &a, hipStream_t s) {

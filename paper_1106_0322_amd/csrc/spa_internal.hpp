@@ -46,7 +46,9 @@ struct GemmArgs {
   void *g;             // M x p likelihood gradient (double for F64, float otherwise)
 };
 
+// The contraction kernel, then (when S > 1) the ordered combination of the split partials.
 hipError_t launch_loglik(const GemmArgs &a, hipStream_t s);
+hipError_t launch_gemm_finalize(const GemmArgs &a, hipStream_t s);
 
 // Position of individual i (0 <= i < xt_group) inside a group of the marker-major genotype
 // copy, chosen so that the K slots of a lane's adjoint MFMA fragment are contiguous in LDS:

@@ -172,6 +172,8 @@ __global__ void pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int
 
 // One proposal sweep: beta' from beta (random walk or MALA), the B operand of beta',
 // and per-particle log prior terms.  Lane l handles markers 4l..4l+3 (one Philox block).
+// The prior and proposal arithmetic runs in the particle precision PT; the log prior of
+// a block of four coefficients is one log of the product of their factors.
 template <Prec P, typename PT, bool MALA>
 __global__ void propose_kernel(ProposeArgs a) {
   using BT = typename BPack<P>::BT;
@@ -185,8 +187,12 @@ __global__ void propose_kernel(ProposeArgs a) {
   BT *Blo = reinterpret_cast<BT *>(a.Blo);
   const int p = a.p, PP = a.PP;
   const bool live = i < a.M;
-  double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
   const Prior pr = a.prior;
+  const PT inv_ac = pr.inf ? PT(0) : static_cast<PT>(1.0 / (pr.a * pr.lam));
+  const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
+  const PT inv_c = static_cast<PT>(1.0 / pr.lam);
+  const PT step = static_cast<PT>(a.step), sqrt_step = static_cast<PT>(a.sqrt_step);
+  double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
   for (int b0 = lane * 4; b0 < PP; b0 += 256) {
     PT z[4] = {0, 0, 0, 0};
     if (live && b0 < p) {
@@ -197,32 +203,34 @@ __global__ void propose_kernel(ProposeArgs a) {
       box_muller(w.x, w.y, z[0], z[1]);
       box_muller(w.z, w.w, z[2], z[3]);
     }
+    PT fc = PT(1), fp = PT(1), lc = PT(0), lpn = PT(0), q = PT(0);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = b0 + q;
+    for (int k = 0; k < 4; ++k) {
+      const int j = b0 + k;
       double bj = 0.0;
       if (live && j < p) {
         const size_t off = (size_t)i * p + j;
-        const double cur = static_cast<double>(beta[off]);
-        const double sg = a.sigma[j];
+        const PT cur = beta[off];
+        const PT sg = static_cast<PT>(a.sigma[j]);
         PT nv;
-        double meanf = cur;
         if constexpr (MALA) {
-          const double g = static_cast<double>(gl[off]) + gt_grad(cur, pr);
-          meanf = cur + 0.5 * a.step * sg * sg * g;
-          nv = static_cast<PT>(meanf + a.sqrt_step * sg * static_cast<double>(z[q]));
+          const PT g = gl[off] + gt_grad_t<PT>(cur, a1, ac, pr.inf, inv_c);
+          const PT meanf = cur + PT(0.5) * step * sg * sg * g;
+          nv = meanf + sqrt_step * sg * z[k];
+          const PT d = nv - meanf;
+          q += d * d / (PT(2) * step * sg * sg);
         } else {
-          nv = static_cast<PT>(cur + a.step * sg * static_cast<double>(z[q]));
+          nv = cur + step * sg * z[k];
         }
         prop[off] = nv;
-        const double nvd = static_cast<double>(nv);
-        if constexpr (MALA) {
-          const double d = nvd - meanf;
-          lqf -= d * d / (2.0 * a.step * sg * sg);
+        if (pr.inf) {
+          lc += fabs(cur);
+          lpn += fabs(nv);
+        } else {
+          fc *= gt_factor<PT>(cur, inv_ac);
+          fp *= gt_factor<PT>(nv, inv_ac);
         }
-        lpc += gt_logpdf(cur, pr);
-        lpp += gt_logpdf(nvd, pr);
-        bj = nvd * a.cc.inv_s[j];
+        bj = static_cast<double>(nv) * a.cc.inv_s[j];
       }
       if (j < PP) {
         double used;
@@ -231,6 +239,14 @@ __global__ void propose_kernel(ProposeArgs a) {
         ybv += a.cc.ytil[j] * a.cc.s[j] * used;
       }
     }
+    if (pr.inf) {
+      lpc += static_cast<double>(lc);
+      lpp += static_cast<double>(lpn);
+    } else {
+      lpc += static_cast<double>(fast_log(fc));
+      lpp += static_cast<double>(fast_log(fp));
+    }
+    lqf -= static_cast<double>(q);
   }
   m = wave_sum(m);
   ybv = wave_sum(ybv);
@@ -241,8 +257,11 @@ __global__ void propose_kernel(ProposeArgs a) {
     a.moff[i] = m;
     a.yb[i] = ybv;
     if (live) {
-      a.lp_cur[i] = lpc;
-      a.lp_prop[i] = lpp;
+      // sum_j log Gt = -p log(2c) - (a+1) sum log(factors)   (or - sum |b| / c)
+      const double base = -static_cast<double>(p) * pr.log2lam;
+      const double scale = pr.inf ? 1.0 / pr.lam : pr.a + 1.0;
+      a.lp_cur[i] = base - scale * lpc;
+      a.lp_prop[i] = base - scale * lpp;
       a.lqf[i] = lqf;
     }
   }
@@ -262,16 +281,19 @@ __global__ void accept_kernel(AcceptArgs a) {
   const Prior pr = a.prior;
   double lqr = 0.0;
   if constexpr (MALA) {
+    const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
+    const PT inv_c = static_cast<PT>(1.0 / pr.lam), step = static_cast<PT>(a.step);
+    PT q = PT(0);
     for (int j = lane; j < p; j += 64) {
       const size_t off = (size_t)i * p + j;
-      const double nv = static_cast<double>(prop[off]);
-      const double sg = a.sigma[j];
-      const double g = static_cast<double>(glp[off]) + gt_grad(nv, pr);
-      const double meanr = nv + 0.5 * a.step * sg * sg * g;
-      const double d = static_cast<double>(beta[off]) - meanr;
-      lqr -= d * d / (2.0 * a.step * sg * sg);
+      const PT nv = prop[off];
+      const PT sg = static_cast<PT>(a.sigma[j]);
+      const PT g = glp[off] + gt_grad_t<PT>(nv, a1, ac, pr.inf, inv_c);
+      const PT meanr = nv + PT(0.5) * step * sg * sg * g;
+      const PT d = beta[off] - meanr;
+      q += d * d / (PT(2) * step * sg * sg);
     }
-    lqr = wave_sum(lqr);
+    lqr = -wave_sum(static_cast<double>(q));
   }
   const double log_alpha = a.ll_prop[i] - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
   const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
@@ -291,9 +313,10 @@ __global__ void accept_kernel(AcceptArgs a) {
 
 // ================================================================ weights
 
-// logw_i += sum_j [log Gt(beta_ij | a, lam_new) - log Gt(beta_ij | a, lam_old)], written as
-// a log(r) - (a+1) log((a lam_new + |b|)/(a lam_old + |b|)) per coefficient, r = lam_new/lam_old
-// (and log(1/r) - |b| (1/lam_new - 1/lam_old) for the double exponential).
+// logw_i += sum_j [log Gt(beta_ij | a, lam_new) - log Gt(beta_ij | a, lam_old)], in FP64:
+//   = p a log r - (a+1) log prod_j (a lam_new + |b_ij|)/(a lam_old + |b_ij|),  r = lam_new/lam_old,
+// each lane forming the product of its (at most 8) ratios, all in (r, 1], before one log;
+// the double exponential: p log(1/r) - (1/lam_new - 1/lam_old) sum_j |b_ij|.
 template <typename PT>
 __global__ void reweight_kernel(const PT *__restrict__ beta, int M, int p, double a, int a_inf,
                                 double lam_new, double lam_old, double *__restrict__ logw) {
@@ -303,17 +326,20 @@ __global__ void reweight_kernel(const PT *__restrict__ beta, int M, int p, doubl
   const double lr = log(lam_new / lam_old);
   double d = 0.0;
   if (a_inf) {
-    const double dl = 1.0 / lam_new - 1.0 / lam_old;
-    for (int j = lane; j < p; j += 64) d += -lr - fabs(static_cast<double>(beta[(size_t)i * p + j])) * dl;
+    double sx = 0.0;
+    for (int j = lane; j < p; j += 64) sx += fabs(static_cast<double>(beta[(size_t)i * p + j]));
+    d = -(1.0 / lam_new - 1.0 / lam_old) * sx;
   } else {
     const double an = a * lam_new, ao = a * lam_old;
+    double prod = 1.0;
     for (int j = lane; j < p; j += 64) {
       const double x = fabs(static_cast<double>(beta[(size_t)i * p + j]));
-      d += a * lr - (a + 1.0) * log((an + x) / (ao + x));
+      prod *= (an + x) / (ao + x);
     }
+    d = -(a + 1.0) * log(prod);
   }
   d = wave_sum(d);
-  if (lane == 0) logw[i] += d;
+  if (lane == 0) logw[i] += d + static_cast<double>(p) * (a_inf ? -lr : a * lr);
 }
 
 // ---- single-workgroup reductions (1024 threads, fixed order)
@@ -461,25 +487,30 @@ __global__ void gather_kernel(const int *__restrict__ anc, int M, int p, const P
 // ---- weighted moments per coefficient (two kernels: chunk partials, ordered combine).
 // Partial sums are shifted by the first particle's row (removes cancellation):
 //   S0 = sum W, S1_j = sum W (b_ij - c_j), S2_j = sum W (b_ij - c_j)^2.
+// A workgroup covers 64 columns and one chunk of at most 256 rows; W_i = exp(logw_i) is
+// evaluated once per row into LDS.
 template <typename PT>
 __global__ void moments_partial_kernel(const PT *__restrict__ beta, const double *__restrict__ logw,
                                        int M, int p, int rows_per_chunk, double *__restrict__ part) {
+  __shared__ double Wsh[256];
+  __shared__ double sh[3][4][64];
   const int col = blockIdx.x * 64 + (threadIdx.x & 63);
   const int rg = threadIdx.x >> 6;   // 4 row groups
   const int chunk = blockIdx.y;
   const int r0 = chunk * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
+  if (r0 + (int)threadIdx.x < r1) Wsh[threadIdx.x] = exp(logw[r0 + threadIdx.x]);
+  __syncthreads();
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   const double c = (col < p) ? static_cast<double>(beta[col]) : 0.0;
   for (int i = r0 + rg; i < r1; i += 4) {
-    const double W = exp(logw[i]);
+    const double W = Wsh[i - r0];
     s0 += W;
     if (col < p) {
-      const double d = static_cast<double>(beta[(size_t)i * p + col]) - c;
-      s1 += W * d;
-      s2 += W * d * d;
+      const double dd = static_cast<double>(beta[(size_t)i * p + col]) - c;
+      s1 += W * dd;
+      s2 += W * dd * dd;
     }
   }
-  __shared__ double sh[3][4][64];
   sh[0][rg][threadIdx.x & 63] = s0;
   sh[1][rg][threadIdx.x & 63] = s1;
   sh[2][rg][threadIdx.x & 63] = s2;
@@ -499,20 +530,26 @@ __global__ void moments_partial_kernel(const PT *__restrict__ beta, const double
   }
 }
 
+// One wave per coefficient: lanes take the chunks (fixed tree order).
 template <typename PT>
 __global__ void moments_final_kernel(const PT *__restrict__ beta, const double *__restrict__ part,
                                      int nchunks, int p, double *__restrict__ mean,
                                      double *__restrict__ var, double *__restrict__ sigma,
                                      double sigma_floor) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (j >= p) return;
   double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-  for (int c = 0; c < nchunks; ++c) {
+  for (int c = lane; c < nchunks; c += 64) {
     const double *o = part + ((size_t)c * p + j) * 3;
     t0 += o[0];
     t1 += o[1];
     t2 += o[2];
   }
+  t0 = wave_sum(t0);
+  t1 = wave_sum(t1);
+  t2 = wave_sum(t2);
+  if (lane != 0) return;
   const double d1 = t1 / t0;
   const double m = static_cast<double>(beta[j]) + d1;
   const double v = fmax(t2 / t0 - d1 * d1, 0.0);
@@ -691,7 +728,7 @@ void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void
                        (float *)dst, (const float *)gsrc, (float *)gdst, llsrc, lldst);
 }
 
-int moments_chunks(int M) { return std::max(1, std::min(256, (M + 255) / 256)); }
+int moments_chunks(int M) { return std::max(1, (M + 255) / 256); }
 
 void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
                     double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st) {
@@ -701,12 +738,12 @@ void launch_moments(bool f64, const void *beta, const double *logw, int M, int p
   if (f64) {
     hipLaunchKernelGGL(moments_partial_kernel<double>, grid, dim3(256), 0, st, (const double *)beta, logw, M, p,
                        rpc, part);
-    hipLaunchKernelGGL(moments_final_kernel<double>, dim3((p + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(moments_final_kernel<double>, dim3((p + 3) / 4), dim3(256), 0, st,
                        (const double *)beta, part, nch, p, mean, var, sigma, sigma_floor);
   } else {
     hipLaunchKernelGGL(moments_partial_kernel<float>, grid, dim3(256), 0, st, (const float *)beta, logw, M, p,
                        rpc, part);
-    hipLaunchKernelGGL(moments_final_kernel<float>, dim3((p + 255) / 256), dim3(256), 0, st,
+    hipLaunchKernelGGL(moments_final_kernel<float>, dim3((p + 3) / 4), dim3(256), 0, st,
                        (const float *)beta, part, nch, p, mean, var, sigma, sigma_floor);
   }
 }
