@@ -78,18 +78,23 @@ struct GT<Prec::F64> {
   }
 };
 
-// Tile shape per precision and padded marker count.
+// Tile shape per precision and padded marker count.  Each wave owns 16 particles (one
+// MFMA column block); a workgroup has NW waves.  With PP <= 256 the BF16 and FP32 variants
+// fit two waves per SIMD (8 per workgroup), so one wave's elementwise VALU work overlaps
+// the other's MFMAs; wider rows (and FP64) keep one wave per SIMD.
 template <Prec P, int PP>
 struct Shape {
   static constexpr int NT = (P == Prec::BF16X2) ? (PP <= 256 ? 64 : 32) : 16;   // individuals
-  static constexpr int PB = (P == Prec::F64) ? 1 : (PP <= 256 ? 2 : 1);         // 16-particle blocks per wave
-  static constexpr int WGP = 4 * 16 * PB;                                        // particles per workgroup
+  static constexpr int PB = 1;                                                   // 16-particle blocks per wave
+  static constexpr int NW = (P != Prec::F64 && PP <= 256) ? 8 : 4;               // waves per workgroup
+  static constexpr int NTHR = 64 * NW;
+  static constexpr int WGP = NW * 16 * PB;                                       // particles per workgroup
 };
 
 // LDS stage layout in 16-byte chunks ("slots").  The individual-major tile has NT rows of
 // CPR = PP*es/16 chunks and the marker-major tile PP rows of CPT = NT*es/16 chunks; each row
 // is padded by one chunk (odd stride: the 16-byte fragment reads of 16 consecutive rows hit
-// distinct banks), and each region is rounded up to 256 slots so that every thread moves
+// distinct banks), and each region is rounded up to a multiple of the thread count so that every thread moves
 // exactly one chunk per copy instruction.  Two stages (double buffering).
 template <Prec P, int PP, bool GRAD>
 struct Lds {
@@ -97,8 +102,9 @@ struct Lds {
   static constexpr int NT = Shape<P, PP>::NT;
   static constexpr int CPR = PP * (int)sizeof(LX) / 16, CX = CPR + 1;
   static constexpr int CPT = NT * (int)sizeof(LX) / 16, CT = CPT + 1;
-  static constexpr int XSL = (NT * CX + 255) / 256 * 256;
-  static constexpr int TSL = GRAD ? (PP * CT + 255) / 256 * 256 : 0;
+  static constexpr int NTHR = Shape<P, PP>::NTHR;
+  static constexpr int XSL = (NT * CX + NTHR - 1) / NTHR * NTHR;
+  static constexpr int TSL = GRAD ? (PP * CT + NTHR - 1) / NTHR * NTHR : 0;
   static constexpr int STG = XSL + TSL;
   static constexpr size_t bytes = 2 * (size_t)STG * 16;
 };
@@ -128,10 +134,10 @@ __device__ __forceinline__ void store_fp8_as_bf16(__bf16 *dst, uint4 v) {
   }
 }
 
-// One workgroup per CU (the double-buffered tiles take most of the LDS), so the kernel may
-// use the whole register file.
+// One workgroup per CU (the double-buffered tiles take most of the LDS): NW/4 waves per SIMD.
 template <Prec P, int PP, bool GRAD, bool FP8>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void loglik_kernel(GemmArgs args) {
+__global__ __attribute__((amdgpu_flat_work_group_size(64, (Shape<P, PP>::NTHR))))
+__attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4)))) void loglik_kernel(GemmArgs args) {
   using T = GT<P>;
   using LX = typename T::LX;
   using BT = typename T::BT;
@@ -148,7 +154,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   constexpr int NMB = PP / 16;   // 16-marker blocks of the adjoint
   constexpr int CX = L::CX, CT = L::CT, CPR = L::CPR, CPT = L::CPT;
   constexpr int XSL = L::XSL, TSL = L::TSL, STG = L::STG;
-  constexpr int NQX = XSL / 256, NQT = GRAD ? TSL / 256 : 1;   // copy instructions per thread
+  constexpr int NTHR = SH::NTHR;
+  constexpr int NQX = XSL / NTHR, NQT = GRAD ? TSL / NTHR : 1;   // copy instructions per thread
   static_assert(P != Prec::BF16X2 || IB % 2 == 0, "BF16 adjoint k-step spans two blocks");
   static_assert(P == Prec::BF16X2 || IB == 1, "FP32/FP64 adjoint uses one block per tile");
   static_assert(!FP8 || P == Prec::BF16X2, "FP8 storage feeds the BF16 path");
@@ -201,18 +208,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) spl[pb] = 0.0;
 
-  // ---- tile staging.  Slot q*256 + tid of a region is filled by this thread's q-th copy;
+  // ---- tile staging.  Slot q*NTHR + tid of a region is filled by this thread's q-th copy;
   // its source offset inside a tile does not depend on the tile and is computed once.
   // Padding slots copy the tile's first chunk (never read).
   int xoff[NQX], toff[NQT];
 #pragma unroll
   for (int q = 0; q < NQX; ++q) {
-    const int sl = q * 256 + tid, r = sl / CX, c = sl % CX;
+    const int sl = q * NTHR + tid, r = sl / CX, c = sl % CX;
     xoff[q] = (r < NT && c < CPR) ? r * PP * (int)sizeof(XG) + c * 16 * (int)sizeof(XG) / (int)sizeof(LX) : 0;
   }
 #pragma unroll
   for (int q = 0; q < NQT; ++q) {
-    const int sl = q * 256 + tid, r = sl / CT, c = sl % CT;
+    const int sl = q * NTHR + tid, r = sl / CT, c = sl % CT;
     toff[q] = (GRAD && r < PP && c < CPT) ? r * n_pad * (int)sizeof(XG) + c * 16 * (int)sizeof(XG) / (int)sizeof(LX) : 0;
   }
   const uint8_t *gxk = reinterpret_cast<const uint8_t *>(args.Xk);
@@ -223,25 +230,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   do {                                                                                                   \
     const uint8_t *bx_ = gxk + (size_t)(tile0_) * PP * sizeof(XG);                                       \
     _Pragma("unroll") for (int q = 0; q < NQX; ++q)                                                      \
-      lds_dma16(bx_ + xoff[q], smem + (stage_) * STG + q * 256 + wave * 64);                            \
+      lds_dma16(bx_ + xoff[q], smem + (stage_) * STG + q * NTHR + wave * 64);                           \
     if constexpr (GRAD) {                                                                                \
       const uint8_t *bt_ = gxt + (size_t)(tile0_) * sizeof(XG);                                          \
       _Pragma("unroll") for (int q = 0; q < NQT; ++q)                                                    \
-        lds_dma16(bt_ + toff[q], smem + (stage_) * STG + XSL + q * 256 + wave * 64);                    \
+        lds_dma16(bt_ + toff[q], smem + (stage_) * STG + XSL + q * NTHR + wave * 64);                   \
     }                                                                                                    \
   } while (0)
   // FP8 storage: each 16-byte chunk of codes becomes two BF16 chunks, through registers.
 #define SPA_COPY_FP8(tile0_, stage_)                                                                     \
   do {                                                                                                   \
     __bf16 *sx_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG);                                     \
-    for (int c = tid; c < NT * PP / 16; c += 256) {                                                      \
+    for (int c = tid; c < NT * PP / 16; c += NTHR) {                                                     \
       const int r = c / (PP / 16), cc = c % (PP / 16);                                                   \
       const uint4 v = *reinterpret_cast<const uint4 *>(gxk + (size_t)((tile0_) + r) * PP + cc * 16);     \
       store_fp8_as_bf16(sx_ + (r * CX + 2 * cc) * 8, v);                                                 \
     }                                                                                                    \
     if constexpr (GRAD) {                                                                                \
       __bf16 *st_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG + XSL);                             \
-      for (int c = tid; c < PP * NT / 16; c += 256) {                                                    \
+      for (int c = tid; c < PP * NT / 16; c += NTHR) {                                                   \
         const int r = c / (NT / 16), cc = c % (NT / 16);                                                 \
         const uint4 v = *reinterpret_cast<const uint4 *>(gxt + (size_t)r * n_pad + (tile0_) + cc * 16); \
         store_fp8_as_bf16(st_ + (r * CT + 2 * cc) * 8, v);                                               \
@@ -515,7 +522,7 @@ static hipError_t launch_one(const GemmArgs &a, hipStream_t s) {
   const int tiles_p = (a.M + per_wg - 1) / per_wg;
   const int g8 = 8 / a.S;
   const int grid = 8 * ((tiles_p + g8 - 1) / g8);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, s, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(Shape<P, PP>::NTHR), lds, s, a);
   return hipGetLastError();
 }
 
