@@ -302,18 +302,22 @@ spa_status gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad
   return SPA_OK;
 }
 
-spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g) {
+// The contraction; with finalize = false and S > 1 the partial sums are left for the caller
+// (the MH decision combines them), and *used describes them.
+spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g,
+                    bool finalize = true, GemmArgs *used = nullptr) {
   GemmArgs a;
   spa_status st = gemm_args(h, prec, o, M, grad, ll, g, &a);
   if (st != SPA_OK) return st;
   tbeg(h, SPA_T_LOGLIK);
   SPA_CK(h, launch_loglik(a, h->stream));
   tend(h);
-  if (a.S > 1) {
+  if (a.S > 1 && finalize) {
     tbeg(h, SPA_T_FINALIZE);
     SPA_CK(h, launch_gemm_finalize(a, h->stream));
     tend(h);
   }
+  if (used) *used = a;
   return SPA_OK;
 }
 
@@ -359,9 +363,21 @@ spa_status sweep(spa_smc *h, int t, int s, double lam) {
   tbeg(h, SPA_T_PROPOSE);
   launch_propose(h->prec, mala, pa, h->stream);
   tend(h);
-  spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr);
+  GemmArgs ga;
+  spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr, false, &ga);
   if (st != SPA_OK) return st;
   AcceptArgs aa{};
+  if (ga.S > 1) {   // the MH decision combines the contraction's partial sums itself
+    aa.spl_part = ga.spl_part;
+    aa.g_part = ga.g_part;
+    aa.S = ga.S;
+    aa.PP = ga.PP;
+    aa.Mp = static_cast<size_t>(ga.M_pad);
+    aa.yb = ga.yb;
+    aa.mu = ga.mu;
+    aa.inv_s = ga.inv_s;
+    aa.ytil = ga.ytil;
+  }
   aa.beta = h->beta;
   aa.gl = h->gl;
   aa.prop = h->prop;

@@ -30,6 +30,7 @@ namespace spa {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 template <Prec P>
 struct GT;
@@ -77,6 +78,9 @@ struct GT<Prec::F64> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+
+// LDS fragment reads kept in flight ahead of the MFMAs that consume them (BF16 path).
+constexpr int kPrefetch = 4;
 
 // Tile shape per precision and padded marker count.  Each wave owns 16 particles (one
 // MFMA column block); a workgroup has NW waves.  With PP <= 256 the BF16 and FP32 variants
@@ -176,8 +180,10 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
   const int wbase = ptile * WGP + wave * 16 * PB;
   const int n = args.n, n_pad = args.n_pad;
   const int chunk = ((n_pad + S - 1) / S + NT - 1) / NT * NT;
-  const int i0 = min(n_pad, split * chunk), i1 = min(n_pad, i0 + chunk);
-  const int ntiles = (i1 - i0) / NT;
+  const int i0 = min(n_pad, split * chunk);
+  // tiles holding at least one real individual (n_pad may exceed n by more than a tile)
+  const int i1 = min(min(n_pad, i0 + chunk), (n + NT - 1) / NT * NT);
+  const int ntiles = max(0, (i1 - i0) / NT);
 
   // ---- coefficient fragments: register resident for the whole pass
   FR bh[PB][NKS];
@@ -268,15 +274,20 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
   }
   SPA_LAND();
 
-  for (int it = 0; it < ntiles; ++it) {
+  // One tile: forward -> elementwise -> adjoint per group of QB 16-individual blocks, while the
+  // next tile's copy lands in the other stage.  MASKED: the tile holds padded individuals,
+  // which happens only for the last tile holding real ones (peeled off the main loop, so the
+  // main loop body is one straight block).
+  auto tile_step = [&](const int it, auto masked_c) {
+    constexpr bool MASKED = decltype(masked_c)::value;
     const int tile0 = i0 + it * NT;
     const int stage = it & 1;
     if constexpr (!FP8) {
-      if (it + 1 < ntiles) SPA_ISSUE(tile0 + NT, stage ^ 1);   // lands during this tile's math
+      // unconditional: the last tile re-copies itself into the idle stage (never read)
+      SPA_ISSUE(i0 + min(it + 1, ntiles - 1) * NT, stage ^ 1);
     }
     const uint4 *sX = smem + stage * STG;          // individual-major tile, row stride CX slots
     const uint4 *sXt = sX + XSL;                   // marker-major tile, row stride CT slots
-    const bool tail = tile0 + NT > n;   // uniform: the only tile holding padded individuals
     // ---- per group of QB 16-individual blocks: forward -> elementwise -> adjoint
 #pragma unroll
     for (int q = 0; q < IB / QB; ++q) {
@@ -299,44 +310,53 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
           }
         }
       }
-
-      // elementwise (lane: particle lr of each block, individuals crow(lg, v) of each block)
-      EL sig[GRAD ? QB : 1][PB][4];
+      // Scheduling: keep D k-steps of fragment reads in flight ahead of their MFMAs (the
+      // default schedule waits on every read right before its use).
+      if constexpr (P == Prec::BF16X2) {
+        constexpr int D = kPrefetch;
+        __builtin_amdgcn_sched_group_barrier(0x100, QB * D, 0);
 #pragma unroll
-      for (int pb = 0; pb < PB; ++pb) {
-        if constexpr (P == Prec::F64) {
-          double sp = 0.0;
-#pragma unroll
-          for (int b = 0; b < QB; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const double eta = acc[b][pb][v] - moff[pb];
-              const double e = exp(-fabs(eta));
-              const bool valid = !tail || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n;
-              sp += valid ? fmax(eta, 0.0) + log1p(e) : 0.0;
-              if constexpr (GRAD) sig[b][pb][v] = eta >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);
-            }
-          spl[pb] += sp;
-        } else {
-          float prod = 1.0f, mx = 0.0f;
-#pragma unroll
-          for (int b = 0; b < QB; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const float eta = acc[b][pb][v] - moff[pb];
-              const float e = fast_exp2(-fabsf(eta) * 1.4426950408889634f);
-              if (!tail || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n) {
-                prod = fmaf(prod, e, prod);
-                mx += fmaxf(eta, 0.0f);
-              }
-              if constexpr (GRAD) {
-                const float rc = fast_rcp(1.0f + e);
-                sig[b][pb][v] = eta >= 0.0f ? rc : e * rc;
-              }
-            }
-          spl[pb] += static_cast<double>(mx + 0.6931471805599453f * fast_log2(prod));
+        for (int ks = 0; ks < NKS; ++ks) {
+          __builtin_amdgcn_sched_group_barrier(0x008, QB * PB * 2, 0);
+          if (ks + D < NKS) __builtin_amdgcn_sched_group_barrier(0x100, QB, 0);
         }
       }
+
+      // elementwise (lane: particle lr of each block, individuals crow(lg, v) of each block).
+      // Padded genotype rows, ones column included, are zero: only the softplus sum masks them.
+      EL sig[GRAD ? QB : 1][PB][4];
+#define SPA_ELEMENTWISE(MASKED)                                                                   \
+  _Pragma("unroll") for (int pb = 0; pb < PB; ++pb) {                                             \
+    if constexpr (P == Prec::F64) {                                                               \
+      double sp = 0.0;                                                                            \
+      _Pragma("unroll") for (int b = 0; b < QB; ++b) _Pragma("unroll") for (int v = 0; v < 4; ++v) { \
+        const double eta = acc[b][pb][v] - moff[pb];                                              \
+        const double e = exp(-fabs(eta));                                                         \
+        const bool valid = !(MASKED) || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n;         \
+        sp += valid ? fmax(eta, 0.0) + log1p(e) : 0.0;                                            \
+        if constexpr (GRAD) sig[b][pb][v] = eta >= 0.0 ? 1.0 / (1.0 + e) : e / (1.0 + e);         \
+      }                                                                                           \
+      spl[pb] += sp;                                                                              \
+    } else {                                                                                      \
+      /* reduced precision: the operand carries log2(e), so z = eta log2(e) */                   \
+      float prod = 1.0f, mx = 0.0f;                                                               \
+      _Pragma("unroll") for (int b = 0; b < QB; ++b) _Pragma("unroll") for (int v = 0; v < 4; ++v) { \
+        const float z = acc[b][pb][v] - moff[pb];                                                 \
+        const float e = fast_exp2(-fabsf(z));                                                     \
+        if (!(MASKED) || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n) {                      \
+          prod = fmaf(prod, e, prod);                                                             \
+          mx += fmaxf(z, 0.0f);                                                                   \
+        }                                                                                         \
+        if constexpr (GRAD) {                                                                     \
+          const float rc = fast_rcp(1.0f + e);                                                    \
+          sig[b][pb][v] = z >= 0.0f ? rc : e * rc;                                                \
+        }                                                                                         \
+      }                                                                                           \
+      spl[pb] += static_cast<double>(0.6931471805599453f * (mx + fast_log2(prod)));              \
+    }                                                                                             \
+  }
+      SPA_ELEMENTWISE(MASKED)
+#undef SPA_ELEMENTWISE
 
       // adjoint: G^T (markers x particles) += X_tile^T . sigma^T
       if constexpr (GRAD) {
@@ -346,11 +366,15 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
 #pragma unroll
           for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const float v = sig[j >> 2][pb][j & 3];
-              const __bf16 h = static_cast<__bf16>(v);
-              rh[pb][j] = h;
-              rl[pb][j] = static_cast<__bf16>(v - static_cast<float>(h));
+            for (int j = 0; j < 8; j += 2) {
+              const f32x2 v = {sig[j >> 2][pb][j & 3], sig[j >> 2][pb][(j & 3) + 1]};
+              const bf16x2 h = __builtin_convertvector(v, bf16x2);
+              const f32x2 r = v - __builtin_convertvector(h, f32x2);
+              const bf16x2 l = __builtin_convertvector(r, bf16x2);
+              rh[pb][j] = h[0];
+              rh[pb][j + 1] = h[1];
+              rl[pb][j] = l[0];
+              rl[pb][j + 1] = l[1];
             }
 #pragma unroll
           for (int mb = 0; mb < NMB; ++mb) {
@@ -360,6 +384,15 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
             for (int pb = 0; pb < PB; ++pb) {
               G[pb][mb] = T::mfma(a, rh[pb], G[pb][mb]);
               G[pb][mb] = T::mfma(a, rl[pb], G[pb][mb]);
+            }
+          }
+          {
+            constexpr int D = kPrefetch;
+            __builtin_amdgcn_sched_group_barrier(0x100, D, 1);
+#pragma unroll
+            for (int mb = 0; mb < NMB; ++mb) {
+              __builtin_amdgcn_sched_group_barrier(0x008, PB * 2, 1);
+              if (mb + D < NMB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
             }
           }
         } else {
@@ -383,7 +416,11 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
       if (it + 1 < ntiles) SPA_COPY_FP8(tile0 + NT, stage ^ 1);
     }
     SPA_LAND();
-  }
+  };
+  const bool has_tail = ntiles > 0 && i0 + ntiles * NT > n;
+  const int nfull = ntiles - (has_tail ? 1 : 0);
+  for (int it = 0; it < nfull; ++it) tile_step(it, std::false_type{});
+  if (has_tail) tile_step(nfull, std::true_type{});
 #undef SPA_ISSUE
 #undef SPA_COPY_FP8
 #undef SPA_LAND

@@ -10,6 +10,12 @@ namespace spa {
 
 enum class Prec : int { F64 = 0, F32 = 1, BF16X2 = 2 };
 
+// The reduced-precision contraction works in base 2: its coefficient operand holds
+// (beta/s) log2(e) and its offsets m_i log2(e), so the kernel's exponentials and logarithms
+// need no extra scaling.  FP64 keeps natural units.
+constexpr double kLog2e = 1.44269504088896340736;
+__host__ __device__ constexpr double operand_scale(Prec p) { return p == Prec::F64 ? 1.0 : kLog2e; }
+
 // Padded marker count used by the GEMM operands: the smallest instantiated width that
 // holds the p markers plus the all-ones column kept in the last padded column.
 int gemm_pad_markers(int p, Prec prec);
@@ -31,9 +37,9 @@ struct GemmArgs {
   const void *Xk;      // n_pad x PP genotypes + ones column (storage format)
   const void *Xt;      // PP x n_pad, the transpose
   const void *yv;      // n_pad labels (double for F64, float otherwise), zero padded
-  const void *Bhi;     // M_pad x PP scaled coefficients beta/s (BF16 hi part, or FP32/FP64)
+  const void *Bhi;     // M_pad x PP coefficients (beta/s) operand_scale (BF16 hi part, or FP32/FP64)
   const void *Blo;     // M_pad x PP BF16 lo part (BF16X2 only)
-  const double *moff;  // M_pad offsets m_i = sum_j mu_j beta_ij / s_j
+  const double *moff;  // M_pad offsets m_i = operand_scale sum_j mu_j beta_ij / s_j
   const double *yb;    // M: sum_j (X_std^T y)_j beta_ij
   const double *mu;    // PP (zero padded)
   const double *inv_s; // PP (zero padded)

@@ -102,16 +102,17 @@ __global__ void labels_kernel(const uint8_t *__restrict__ y, int n, int n_pad, E
 }
 
 // ------------------------------------------------- scaled-coefficient operand b = beta/s
-// Writes the B operand of the contraction for one row (already in registers as 4
-// consecutive coefficients per lane) and returns (m, yb) contributions.
+// Writes one coefficient of the B operand of the contraction, scaled by operand_scale(P),
+// and returns in `used` the value the operand actually represents (in the scaled units).
 template <Prec P>
 struct BPack;
 
 template <>
 struct BPack<Prec::BF16X2> {
   using BT = __bf16;
+  static constexpr double scale = kLog2e;
   __device__ static void put(double bj, BT *hi, BT *lo, size_t off, double &used) {
-    const float f = static_cast<float>(bj);
+    const float f = static_cast<float>(bj * scale);
     const __bf16 h = static_cast<__bf16>(f);
     const __bf16 l = static_cast<__bf16>(f - static_cast<float>(h));
     hi[off] = h;
@@ -122,8 +123,9 @@ struct BPack<Prec::BF16X2> {
 template <>
 struct BPack<Prec::F32> {
   using BT = float;
+  static constexpr double scale = kLog2e;
   __device__ static void put(double bj, BT *hi, BT *, size_t off, double &used) {
-    const float f = static_cast<float>(bj);
+    const float f = static_cast<float>(bj * scale);
     hi[off] = f;
     used = static_cast<double>(f);
   }
@@ -131,11 +133,26 @@ struct BPack<Prec::F32> {
 template <>
 struct BPack<Prec::F64> {
   using BT = double;
+  static constexpr double scale = 1.0;
   __device__ static void put(double bj, BT *hi, BT *, size_t off, double &used) {
     hi[off] = bj;
     used = bj;
   }
 };
+
+// Store four consecutive B-operand entries (PP is a multiple of 32, so the block is aligned).
+template <Prec P, typename BT>
+__device__ __forceinline__ void store4_b(BT *hi, BT *lo, size_t off, const BT h[4], const BT l[4]) {
+  if constexpr (P == Prec::BF16X2) {
+    typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<bf16x4_t *>(hi + off) = bf16x4_t{h[0], h[1], h[2], h[3]};
+    *reinterpret_cast<bf16x4_t *>(lo + off) = bf16x4_t{l[0], l[1], l[2], l[3]};
+  } else if constexpr (P == Prec::F32) {
+    *reinterpret_cast<float4 *>(hi + off) = make_float4(h[0], h[1], h[2], h[3]);
+  } else {
+    *reinterpret_cast<f64x4 *>(hi + off) = f64x4{h[0], h[1], h[2], h[3]};
+  }
+}
 
 struct ColConst {
   const double *mu, *s, *inv_s, *ytil;   // PP-padded
@@ -164,11 +181,61 @@ __global__ void pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int
   ybv = wave_sum(ybv);
   if (lane == 0) {
     moff[i] = m;
-    yb[i] = ybv;
+    yb[i] = ybv / BPack<P>::scale;
   }
 }
 
 // ================================================================ move kernels
+
+// Standard normals for a Philox block: Box-Muller in the particle precision.  The FP32 form
+// uses the hardware transcendentals (v_sin/v_cos take the angle in revolutions, which is
+// exactly w * 2^-32 here); the FP64 form is the libm one.
+__device__ __forceinline__ void block_normals(uint4 w, double z[4]) {
+  box_muller(w.x, w.y, z[0], z[1]);
+  box_muller(w.z, w.w, z[2], z[3]);
+}
+__device__ __forceinline__ void block_normals(uint4 w, float z[4]) {
+  const float l0 = __builtin_amdgcn_logf((static_cast<float>(w.x) + 1.0f) * 0x1p-32f);   // log2 u
+  const float l1 = __builtin_amdgcn_logf((static_cast<float>(w.z) + 1.0f) * 0x1p-32f);
+  const float r0 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * l0);                   // sqrt(-2 ln u)
+  const float r1 = __builtin_amdgcn_sqrtf(-1.3862943611198906f * l1);
+  const float t0 = static_cast<float>(w.y) * 0x1p-32f, t1 = static_cast<float>(w.w) * 0x1p-32f;
+  z[0] = r0 * __builtin_amdgcn_cosf(t0);
+  z[1] = r0 * __builtin_amdgcn_sinf(t0);
+  z[2] = r1 * __builtin_amdgcn_cosf(t1);
+  z[3] = r1 * __builtin_amdgcn_sinf(t1);
+}
+
+// Four consecutive values starting at a multiple of 4 (16/32-byte aligned when `vec`).
+template <typename T>
+__device__ __forceinline__ void load4(const T *src, bool vec, int j0, int lim, T out[4]) {
+  if (vec && j0 + 4 <= lim) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *reinterpret_cast<const float4 *>(src + j0);
+      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+    } else {
+      const f64x4 v = *reinterpret_cast<const f64x4 *>(src + j0);
+      out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) out[k] = (j0 + k < lim) ? src[j0 + k] : T(0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void store4(T *dst, bool vec, int j0, int lim, const T v[4]) {
+  if (vec && j0 + 4 <= lim) {
+    if constexpr (sizeof(T) == 4) {
+      *reinterpret_cast<float4 *>(dst + j0) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      *reinterpret_cast<f64x4 *>(dst + j0) = f64x4{v[0], v[1], v[2], v[3]};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (j0 + k < lim) dst[j0 + k] = v[k];
+  }
+}
 
 // One proposal sweep: beta' from beta (random walk or MALA), the B operand of beta',
 // and per-particle log prior terms.  Lane l handles markers 4l..4l+3 (one Philox block).
@@ -180,13 +247,14 @@ __global__ void propose_kernel(ProposeArgs a) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= a.M_pad) return;
-  const PT *beta = reinterpret_cast<const PT *>(a.beta);
-  const PT *gl = reinterpret_cast<const PT *>(a.gl);
-  PT *prop = reinterpret_cast<PT *>(a.prop);
+  const int p = a.p, PP = a.PP;
+  const PT *beta = reinterpret_cast<const PT *>(a.beta) + (size_t)i * p;
+  const PT *gl = reinterpret_cast<const PT *>(a.gl) + (size_t)i * p;
+  PT *prop = reinterpret_cast<PT *>(a.prop) + (size_t)i * p;
   BT *Bhi = reinterpret_cast<BT *>(a.Bhi);
   BT *Blo = reinterpret_cast<BT *>(a.Blo);
-  const int p = a.p, PP = a.PP;
   const bool live = i < a.M;
+  const bool vrow = (p & 3) == 0;   // particle rows keep 4-marker blocks aligned
   const Prior pr = a.prior;
   const PT inv_ac = pr.inf ? PT(0) : static_cast<PT>(1.0 / (pr.a * pr.lam));
   const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
@@ -194,51 +262,59 @@ __global__ void propose_kernel(ProposeArgs a) {
   const PT step = static_cast<PT>(a.step), sqrt_step = static_cast<PT>(a.sqrt_step);
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
   for (int b0 = lane * 4; b0 < PP; b0 += 256) {
-    PT z[4] = {0, 0, 0, 0};
-    if (live && b0 < p) {
-      const uint4 w = philox4x32_10(
-          make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(b0 >> 2), a.sweep,
-                     word3(a.t, kTagNormal)),
-          a.k0, a.k1);
-      box_muller(w.x, w.y, z[0], z[1]);
-      box_muller(w.z, w.w, z[2], z[3]);
+    PT z[4] = {0, 0, 0, 0}, cur[4] = {0, 0, 0, 0}, gv[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
+    double sgd[4], invs[4], mu4[4], yt4[4], s4[4];
+    load4(a.sigma, true, b0, p, sgd);
+    load4(a.cc.inv_s, true, b0, PP, invs);
+    load4(a.cc.mu, true, b0, PP, mu4);
+    load4(a.cc.ytil, true, b0, PP, yt4);
+    load4(a.cc.s, true, b0, PP, s4);
+    const bool act = live && b0 < p;
+    if (act) {
+      block_normals(philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(b0 >> 2), a.sweep,
+                                             word3(a.t, kTagNormal)),
+                                  a.k0, a.k1),
+                    z);
+      load4(beta, vrow, b0, p, cur);
+      if constexpr (MALA) load4(gl, vrow, b0, p, gv);
     }
     PT fc = PT(1), fp = PT(1), lc = PT(0), lpn = PT(0), q = PT(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j = b0 + k;
-      double bj = 0.0;
-      if (live && j < p) {
-        const size_t off = (size_t)i * p + j;
-        const PT cur = beta[off];
-        const PT sg = static_cast<PT>(a.sigma[j]);
-        PT nv;
+      if (act && j < p) {
+        const PT sg = static_cast<PT>(sgd[k]);
         if constexpr (MALA) {
-          const PT g = gl[off] + gt_grad_t<PT>(cur, a1, ac, pr.inf, inv_c);
-          const PT meanf = cur + PT(0.5) * step * sg * sg * g;
-          nv = meanf + sqrt_step * sg * z[k];
-          const PT d = nv - meanf;
+          const PT g = gv[k] + gt_grad_t<PT>(cur[k], a1, ac, pr.inf, inv_c);
+          const PT meanf = cur[k] + PT(0.5) * step * sg * sg * g;
+          nv[k] = meanf + sqrt_step * sg * z[k];
+          const PT d = nv[k] - meanf;
           q += d * d / (PT(2) * step * sg * sg);
         } else {
-          nv = cur + step * sg * z[k];
+          nv[k] = cur[k] + step * sg * z[k];
         }
-        prop[off] = nv;
         if (pr.inf) {
-          lc += fabs(cur);
-          lpn += fabs(nv);
+          lc += fabs(cur[k]);
+          lpn += fabs(nv[k]);
         } else {
-          fc *= gt_factor<PT>(cur, inv_ac);
-          fp *= gt_factor<PT>(nv, inv_ac);
+          fc *= gt_factor<PT>(cur[k], inv_ac);
+          fp *= gt_factor<PT>(nv[k], inv_ac);
         }
-        bj = static_cast<double>(nv) * a.cc.inv_s[j];
-      }
-      if (j < PP) {
-        double used;
-        BPack<P>::put(bj, Bhi, Blo, (size_t)i * PP + j, used);
-        m += a.cc.mu[j] * used;
-        ybv += a.cc.ytil[j] * a.cc.s[j] * used;
       }
     }
+    if (act) store4(prop, vrow, b0, p, nv);
+    // B operand of the proposal (zero in padded markers and padded particles)
+    BT hb[4], lb[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = b0 + k;
+      const double bj = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] : 0.0;
+      double used;
+      BPack<P>::put(bj, hb, lb, k, used);
+      m += mu4[k] * used;
+      ybv += yt4[k] * s4[k] * used;
+    }
+    store4_b<P>(Bhi, Blo, (size_t)i * PP + b0, hb, lb);
     if (pr.inf) {
       lpc += static_cast<double>(lc);
       lpp += static_cast<double>(lpn);
@@ -255,7 +331,7 @@ __global__ void propose_kernel(ProposeArgs a) {
   if constexpr (MALA) lqf = wave_sum(lqf);
   if (lane == 0) {
     a.moff[i] = m;
-    a.yb[i] = ybv;
+    a.yb[i] = ybv / BPack<P>::scale;
     if (live) {
       // sum_j log Gt = -p log(2c) - (a+1) sum log(factors)   (or - sum |b| / c)
       const double base = -static_cast<double>(p) * pr.log2lam;
@@ -268,7 +344,10 @@ __global__ void propose_kernel(ProposeArgs a) {
 }
 
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
-template <typename PT, bool MALA>
+// PARTS: the proposal's log-likelihood and likelihood gradient are combined from the split
+// contraction's partial sums (kept in registers: lane l holds markers l, l+64, ...).
+constexpr int kAccMaxPerLane = 8;   // p <= 511
+template <typename PT, bool MALA, bool PARTS>
 __global__ void accept_kernel(AcceptArgs a) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -279,34 +358,72 @@ __global__ void accept_kernel(AcceptArgs a) {
   const PT *glp = reinterpret_cast<const PT *>(a.gl_prop);
   const int p = a.p;
   const Prior pr = a.prior;
+  double llp;
+  PT gnew[MALA ? kAccMaxPerLane : 1];
+  if constexpr (PARTS) {
+    double spl = 0.0;
+    for (int s = 0; s < a.S; ++s) spl += a.spl_part[s * a.Mp + i];
+    llp = a.yb[i] - spl;
+    if constexpr (MALA) {
+      const PT *gp = reinterpret_cast<const PT *>(a.g_part);
+      double rho = 0.0;
+      for (int s = 0; s < a.S; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * a.PP + a.PP - 1]);
+#pragma unroll
+      for (int k = 0; k < kAccMaxPerLane; ++k) {
+        const int j = lane + 64 * k;
+        if (j < p) {
+          double acc = 0.0;
+          for (int s = 0; s < a.S; ++s) acc += static_cast<double>(gp[(s * a.Mp + i) * a.PP + j]);
+          gnew[k] = static_cast<PT>(a.ytil[j] - (acc - a.mu[j] * rho) * a.inv_s[j]);
+        }
+      }
+    }
+  } else {
+    llp = a.ll_prop[i];
+    if constexpr (MALA) {
+#pragma unroll
+      for (int k = 0; k < kAccMaxPerLane; ++k) {
+        const int j = lane + 64 * k;
+        if (j < p) gnew[k] = glp[(size_t)i * p + j];
+      }
+    }
+  }
   double lqr = 0.0;
   if constexpr (MALA) {
     const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
     const PT inv_c = static_cast<PT>(1.0 / pr.lam), step = static_cast<PT>(a.step);
     PT q = PT(0);
-    for (int j = lane; j < p; j += 64) {
-      const size_t off = (size_t)i * p + j;
-      const PT nv = prop[off];
-      const PT sg = static_cast<PT>(a.sigma[j]);
-      const PT g = glp[off] + gt_grad_t<PT>(nv, a1, ac, pr.inf, inv_c);
-      const PT meanr = nv + PT(0.5) * step * sg * sg * g;
-      const PT d = beta[off] - meanr;
-      q += d * d / (PT(2) * step * sg * sg);
+#pragma unroll
+    for (int k = 0; k < kAccMaxPerLane; ++k) {
+      const int j = lane + 64 * k;
+      if (j < p) {
+        const size_t off = (size_t)i * p + j;
+        const PT nv = prop[off];
+        const PT sg = static_cast<PT>(a.sigma[j]);
+        const PT g = gnew[k] + gt_grad_t<PT>(nv, a1, ac, pr.inf, inv_c);
+        const PT meanr = nv + PT(0.5) * step * sg * sg * g;
+        const PT d = beta[off] - meanr;
+        q += d * d / (PT(2) * step * sg * sg);
+      }
     }
     lqr = -wave_sum(static_cast<double>(q));
   }
-  const double log_alpha = a.ll_prop[i] - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
+  const double log_alpha = llp - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
   const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
                                 a.k0, a.k1);
   const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
   const bool acc = log(u) < log_alpha;   // false for NaN
   if (acc) {
-    for (int j = lane; j < p; j += 64) {
-      const size_t off = (size_t)i * p + j;
-      beta[off] = prop[off];
-      if constexpr (MALA) gl[off] = glp[off];
+#pragma unroll
+    for (int k = 0; k < kAccMaxPerLane; ++k) {
+      const int j = lane + 64 * k;
+      if (j < p) {
+        const size_t off = (size_t)i * p + j;
+        beta[off] = prop[off];
+        if constexpr (MALA) gl[off] = gnew[k];
+      }
     }
-    if (lane == 0) a.ll[i] = a.ll_prop[i];
+    if (lane == 0) a.ll[i] = llp;
   }
   if (lane == 0) a.acc_cnt[i] += acc ? 1 : 0;
 }
@@ -691,15 +808,22 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) 
 #undef SPA_PROP
 }
 
-void launch_accept(bool f64, bool mala, const AcceptArgs &a, hipStream_t st) {
+template <typename PT>
+static void launch_accept_t(bool mala, const AcceptArgs &a, hipStream_t st) {
   const int grid = grid_rows(a.M, 4);
-  if (f64) {
-    if (mala) hipLaunchKernelGGL((accept_kernel<double, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((accept_kernel<double, false>), dim3(grid), dim3(256), 0, st, a);
+  const bool parts = a.spl_part != nullptr;
+  if (mala) {
+    if (parts) hipLaunchKernelGGL((accept_kernel<PT, true, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((accept_kernel<PT, true, false>), dim3(grid), dim3(256), 0, st, a);
   } else {
-    if (mala) hipLaunchKernelGGL((accept_kernel<float, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((accept_kernel<float, false>), dim3(grid), dim3(256), 0, st, a);
+    if (parts) hipLaunchKernelGGL((accept_kernel<PT, false, true>), dim3(grid), dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((accept_kernel<PT, false, false>), dim3(grid), dim3(256), 0, st, a);
   }
+}
+
+void launch_accept(bool f64, bool mala, const AcceptArgs &a, hipStream_t st) {
+  if (f64) launch_accept_t<double>(mala, a, st);
+  else launch_accept_t<float>(mala, a, st);
 }
 
 void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,

@@ -36,6 +36,14 @@ struct AcceptArgs {
   const void *prop, *gl_prop;       // M x p proposal and its likelihood gradient
   double *ll;                       // M state log-likelihood (updated)
   const double *ll_prop, *lp_cur, *lp_prop, *lqf;
+  // When the contraction ran in S > 1 individual ranges, its per-range partial sums are
+  // combined here (same order and arithmetic as the finalize kernel) instead of reading
+  // ll_prop / gl_prop: spl_part is S x Mp softplus sums, g_part S x Mp x PP adjoint sums.
+  const double *spl_part;           // null: read ll_prop / gl_prop
+  const void *g_part;
+  int S, PP;
+  size_t Mp;
+  const double *yb, *mu, *inv_s, *ytil;
   const double *sigma;
   int *acc_cnt;
   Prior prior;
