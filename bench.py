@@ -56,6 +56,19 @@ def profiled_traffic(workload: str):
     return int(kv["hbm_bytes_per_launch"])
 
 
+def copy_calibration():
+    """A plain device copy of known size: 64 Mi float32 (256 MiB read, 256 MiB written),
+    three times.  Its FETCH_SIZE / WRITE_SIZE readings scale the contraction's counters."""
+    import torch
+    n = 64 * 1024 * 1024
+    x = torch.ones(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(f"copied 3 x {n * 4} bytes", flush=True)
+
+
 def gemm_flops(cfg) -> float:
     """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
     f = 2.0 * cfg.N * cfg.n * cfg.p
@@ -157,11 +170,17 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")
     ap.add_argument("--ess-seeds", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device copy three times (the reference "
+                         "launch for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sampler "
-              "shards particles across GPUs only by design, not in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding the "
+              "particles across GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
     from paper_1106_0322_amd import SamplerConfig, SpaSMC
