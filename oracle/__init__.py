@@ -21,10 +21,13 @@ definition it cites:
                     likelihood ratios, systematic resampling, random-walk and MALA moves,
                     weighted moments and the scale-adaptation rule.
 * ``quadrature`` -- brute-force posterior means and log marginal likelihoods for p = 1, 2.
+* ``spa``        -- the sparsity-path summaries (Section 5): weighted quantiles (absolute
+                    medians, credible intervals), concentrations, the posterior over the
+                    scale and the c-marginal mixture (Section 4, eq. all_particles).
 
 Parity status: every function here is pinned by the CPU tests (closed forms,
 library special cases, invariants, brute force, published known-answer vectors);
 posterior-mean paths at p >= 10 are pinned only statistically (there is no closed
 form), see the test-suite.
 """
-from . import gt_prior, likelihood, philox, smc, quadrature  # noqa: F401
+from . import gt_prior, likelihood, philox, smc, quadrature, spa  # noqa: F401
