@@ -160,6 +160,63 @@ spa_status spa_smc_resample(spa_smc *h, const double *w_dev, int32_t M, uint32_t
                             int32_t *ancestors_dev);
 
 /*
+ * Sparsity-path summaries (Section 5: absolute-median paths, credible intervals,
+ * concentration plots, the posterior over the scale and the c-marginal summaries of the
+ * marginal plots, the mixture being eq. all_particles of Section 4).
+ *
+ * Definitions shared by the calls below.  The weights are quantised to integers
+ * q_i = floor((w_i / max w) * 2^K), K = 63 - ceil(log2 M), so every cumulative sum is an
+ * exact 64-bit integer.  For a level alpha in (0, 1] the weighted quantile of a column is
+ * the smallest value whose cumulative q (values in ascending order, -0 = +0) reaches
+ * ceil(alpha * C), C = sum q, with alpha taken as the exact rational its double denotes.
+ * The concentration for a tolerance Delta > 0 is V = 1 - S / C, S = sum of q_i over
+ * |value_i| < Delta (open interval), the division in FP64.  Both are bit-exact with a
+ * sequential evaluation of the same definitions.  At most 8 levels and 8 tolerances.
+ */
+
+/*
+ * spa_weighted_summaries -- quantiles and concentrations of every column of one weighted
+ * set.  values_dev: M x p row-major (FP64 if values_are_fp64 else FP32), finite;
+ * w_dev: M doubles (>= 0, finite, not all zero; need not sum to one).  levels (L) and
+ * deltas (D) are host arrays.  quant_dev: L x p doubles, conc_dev: D x p doubles (device
+ * outputs, either NULL when its count is 0).  Works on the handle's stream and blocks
+ * until done.  Errors: SPA_ERR_ARG (null pointers, more than 8 levels/tolerances, a
+ * level outside (0, 1], a tolerance <= 0), SPA_ERR_SHAPE (M or p < 1), SPA_ERR_NUMERIC
+ * (invalid weights; outputs then undefined).
+ */
+spa_status spa_weighted_summaries(spa_smc *h, const void *values_dev, int32_t M, int32_t p,
+                                  int32_t values_are_fp64, const double *w_dev, const double *levels,
+                                  int32_t L, const double *deltas, int32_t D, double *quant_dev,
+                                  double *conc_dev);
+
+/*
+ * spa_smc_set_summaries -- from now on, after the moves of every scale t (and at once
+ * for the current scale) record the quantiles (levels, L) and concentrations (deltas, D)
+ * of each coefficient under the particles' normalised weights W_t: row t-1 of a
+ * T x L x p and a T x D x p device array.  keep_history != 0 also keeps every scale's
+ * particles and log weights (T x N x p + T x N device memory) for
+ * spa_smc_marginal_summaries; it must then be called at the first scale.  Once per
+ * handle.  Errors: SPA_ERR_ARG (as above), SPA_ERR_STATE, SPA_ERR_ALLOC.
+ */
+spa_status spa_smc_set_summaries(spa_smc *h, const double *levels, int32_t L, const double *deltas,
+                                 int32_t D, int32_t keep_history);
+
+/* Borrow the per-scale summary paths (rows 0..t-1 filled); either pointer may be NULL. */
+spa_status spa_smc_get_summaries(const spa_smc *h, const double **quant_path_dev,
+                                 const double **conc_path_dev);
+
+/*
+ * spa_smc_marginal_summaries -- summaries of the c-marginal posterior over the scales
+ * 1..t run so far: the mixture of the weighted sets with weights proportional to
+ * (Z_s / Z_1) W_s,i (a uniform prior on log c over the geometric grid), evaluated as
+ * exp(log Z_s - max log Z + log W_s,i).  quant_dev: L x p, conc_dev: D x p, and
+ * scale_post_dev (nullable): t doubles, p(c = lambda_s | X, y, a) = Z_s / sum Z.
+ * Blocks until done.  Errors: SPA_ERR_STATE without a kept history, SPA_ERR_ARG.
+ */
+spa_status spa_smc_marginal_summaries(spa_smc *h, double *quant_dev, double *conc_dev,
+                                      double *scale_post_dev);
+
+/*
  * spa_smc_get -- borrow the current state: particles (N x p, FP64 for SPA_PREC_FP64
  * else FP32), normalised log weights (N doubles), the per-scale weighted mean and
  * variance of every coefficient (T x p doubles each, rows 0..t-1 filled) and the host
@@ -209,7 +266,8 @@ enum {
   SPA_T_GATHER = 5,     /* particle gather after resampling                            */
   SPA_T_MOMENTS = 6,    /* weighted moments                                            */
   SPA_T_FINALIZE = 7,   /* ordered sum of the contraction's split partials             */
-  SPA_TIMING_CLASSES = 8
+  SPA_T_SUMMARY = 8,    /* sparsity-path summaries (quantiles, concentrations)         */
+  SPA_TIMING_CLASSES = 9
 };
 spa_status spa_smc_set_timing(spa_smc *h, int32_t enable);
 spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches);

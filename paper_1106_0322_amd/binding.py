@@ -27,10 +27,12 @@ MOVE = {"rwm": 0, "mala": 1}
 
 # The exported C entry points (kept in step with include/spa_smc.h).
 EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "spa_smc_resample",
+           "spa_weighted_summaries", "spa_smc_set_summaries", "spa_smc_get_summaries",
+           "spa_smc_marginal_summaries",
            "spa_smc_get", "spa_smc_get_stats", "spa_smc_set_state", "spa_philox4x32_10",
            "spa_smc_set_timing", "spa_smc_get_timing", "spa_smc_destroy", "spa_smc_last_error"]
 TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments",
-                  "finalize"]
+                  "finalize", "summary"]
 
 
 class SpaError(RuntimeError):
@@ -80,6 +82,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spa_smc_loglik.argtypes = [vp, vp, i32, i32, ctypes.c_int, vp]
     lib.spa_smc_grad.argtypes = [vp, vp, i32, i32, dbl, ctypes.c_int, vp, vp]
     lib.spa_smc_resample.argtypes = [vp, vp, i32, ctypes.c_uint32, vp]
+    dptr = ctypes.POINTER(ctypes.c_double)
+    lib.spa_weighted_summaries.argtypes = [vp, vp, i32, i32, i32, vp, dptr, i32, dptr, i32, vp, vp]
+    lib.spa_smc_set_summaries.argtypes = [vp, dptr, i32, dptr, i32, i32]
+    lib.spa_smc_get_summaries.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
+    lib.spa_smc_marginal_summaries.argtypes = [vp, vp, vp, vp]
     lib.spa_smc_get.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
     lib.spa_smc_get_stats.argtypes = [vp, i32, ctypes.POINTER(_Stats)]
@@ -283,6 +290,63 @@ class SpaSMC:
         anc = torch.empty(w.shape[0], dtype=torch.int32, device=self.device)
         self._check(self.lib.spa_smc_resample(self.h, _ptr(w), w.shape[0], ctypes.c_uint32(u32), _ptr(anc)))
         return anc
+
+    # ------------------------------------------------------ sparsity-path summaries
+    @staticmethod
+    def _dbl_array(v):
+        v = [float(x) for x in v]
+        return (ctypes.c_double * max(1, len(v)))(*v), len(v)
+
+    def weighted_summaries(self, values, w, levels=(0.05, 0.5, 0.95), deltas=(0.05, 0.1)):
+        """Weighted quantiles (len(levels) x p) and concentrations (len(deltas) x p) of
+        every column of values (M x p, FP32 or FP64) under weights w (M)."""
+        torch = _torch()
+        values = values.to(self.device).contiguous()
+        if values.dim() == 1:
+            values = values[:, None]
+        assert values.dtype in (torch.float32, torch.float64)
+        w = w.to(device=self.device, dtype=torch.float64).contiguous()
+        M, p = values.shape
+        la, L = self._dbl_array(levels)
+        da, D = self._dbl_array(deltas)
+        q = torch.empty((L, p), dtype=torch.float64, device=self.device)
+        c = torch.empty((D, p), dtype=torch.float64, device=self.device)
+        self._check(self.lib.spa_weighted_summaries(self.h, _ptr(values), M, p, int(values.dtype == torch.float64),
+                                                    _ptr(w), la, L, da, D, _ptr(q) if L else None,
+                                                    _ptr(c) if D else None))
+        return q, c
+
+    def set_summaries(self, levels=(0.05, 0.5, 0.95), deltas=(0.05, 0.1), keep_history: bool = False):
+        la, L = self._dbl_array(levels)
+        da, D = self._dbl_array(deltas)
+        self._levels, self._deltas = list(levels), list(deltas)
+        self._check(self.lib.spa_smc_set_summaries(self.h, la, L, da, D, int(bool(keep_history))))
+
+    def summaries(self):
+        """Per-scale quantile (t x L x p) and concentration (t x D x p) paths, on the host."""
+        torch = _torch()
+        qp, cp = ctypes.c_void_p(), ctypes.c_void_p()
+        self._check(self.lib.spa_smc_get_summaries(self.h, ctypes.byref(qp), ctypes.byref(cp)))
+        _, _, _, _, _, t = self._get()
+        T, p = len(self._lam), self.cfg.p
+        L, D = len(self._levels), len(self._deltas)
+        q = self._copy_dev(qp, T * L * p, torch.float64).view(T, L, p) if L else None
+        c = self._copy_dev(cp, T * D * p, torch.float64).view(T, D, p) if D else None
+        self.stream.synchronize()
+        return (q[:t].cpu().numpy() if L else None), (c[:t].cpu().numpy() if D else None)
+
+    def marginal_summaries(self):
+        """Quantiles (L x p) and concentrations (D x p) of the c-marginal mixture over the
+        scales run so far, and the posterior over those scales (t,)."""
+        torch = _torch()
+        _, _, _, _, _, t = self._get()
+        p, L, D = self.cfg.p, len(self._levels), len(self._deltas)
+        q = torch.empty((L, p), dtype=torch.float64, device=self.device)
+        c = torch.empty((D, p), dtype=torch.float64, device=self.device)
+        sp = torch.empty(t, dtype=torch.float64, device=self.device)
+        self._check(self.lib.spa_smc_marginal_summaries(self.h, _ptr(q) if L else None, _ptr(c) if D else None,
+                                                        _ptr(sp)))
+        return q.cpu().numpy(), c.cpu().numpy(), sp.cpu().numpy()
 
     def set_timing(self, enable: bool = True):
         self._check(self.lib.spa_smc_set_timing(self.h, int(bool(enable))))

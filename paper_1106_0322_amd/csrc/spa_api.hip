@@ -12,6 +12,7 @@
 #include "../../include/spa_smc.h"
 #include "spa_internal.hpp"
 #include "spa_kernels.hpp"
+#include "spa_summary.hpp"
 
 using namespace spa;
 
@@ -114,6 +115,23 @@ struct spa_smc {
   std::vector<int> ev_cat;         // category of each recorded pair
   double t_ms[SPA_TIMING_CLASSES] = {0};
   long long t_cnt[SPA_TIMING_CLASSES] = {0};
+  // sparsity-path summaries (per scale, and the c-marginal mixture)
+  SqLevels sq_lv{};
+  bool sq_on = false, sq_keep = false;
+  double *quant_path = nullptr, *conc_path = nullptr;   // T x L x p, T x D x p
+  void *hist_beta = nullptr;                            // T x N x p particles after the moves
+  double *hist_logw = nullptr;                          // T x N normalised log weights
+  uint64_t *sq_q = nullptr;
+  size_t sq_q_cap = 0;
+  void *sq_keys = nullptr;
+  size_t sq_keys_cap = 0;                               // bytes
+  SqState *sq_st = nullptr;
+  SqSel *sq_sel = nullptr;
+  unsigned long long *sq_hist = nullptr, *sq_inside = nullptr;
+  int sq_p_cap = 0;
+  double *sq_w = nullptr, *sq_logz = nullptr;
+  size_t sq_w_cap = 0;
+  SqState *hsq_st = nullptr;                            // pinned host
   // path
   int t = 0;
   double log_z = 0.0;
@@ -431,6 +449,103 @@ spa_status record_moments(spa_smc *h, int row) {
   return SPA_OK;
 }
 
+// Summary scratch for M values of p coefficients.
+spa_status ensure_sq(spa_smc *h, size_t M, int p, bool f64) {
+  spa_status st;
+  if (h->sq_q_cap < M) {
+    dfree(h, h->sq_q);
+    h->sq_q = nullptr;
+    if ((st = dalloc(h, &h->sq_q, 8 * M)) != SPA_OK) return st;
+    h->sq_q_cap = M;
+  }
+  const size_t kb = M * (size_t)p * sq_key_bytes(f64);
+  if (h->sq_keys_cap < kb) {
+    dfree(h, h->sq_keys);
+    h->sq_keys = nullptr;
+    if ((st = dalloc(h, &h->sq_keys, kb)) != SPA_OK) return st;
+    h->sq_keys_cap = kb;
+  }
+  if (h->sq_p_cap < p) {
+    dfree(h, h->sq_sel);
+    dfree(h, h->sq_hist);
+    dfree(h, h->sq_inside);
+    h->sq_sel = nullptr;
+    h->sq_hist = nullptr;
+    h->sq_inside = nullptr;
+    if ((st = dalloc(h, &h->sq_sel, sizeof(SqSel) * (size_t)p * kSqMaxLevels)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->sq_hist, 8 * (size_t)p * kSqMaxLevels * 256)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->sq_inside, 8 * (size_t)p * kSqMaxLevels)) != SPA_OK) return st;
+    h->sq_p_cap = p;
+  }
+  if (!h->sq_st && (st = dalloc(h, &h->sq_st, sizeof(SqState))) != SPA_OK) return st;
+  return SPA_OK;
+}
+
+spa_status run_summaries(spa_smc *h, const void *values, bool f64, int M, int p, const double *w, bool logw,
+                         const SqLevels &lv, double *quant, double *conc) {
+  spa_status st;
+  if ((st = ensure_sq(h, (size_t)M, p, f64)) != SPA_OK) return st;
+  SqArgs a{};
+  a.values = values;
+  a.f64 = f64;
+  a.M = M;
+  a.p = p;
+  a.w = w;
+  a.log_weights = logw;
+  a.lv = lv;
+  a.q = h->sq_q;
+  a.keys = h->sq_keys;
+  a.st = h->sq_st;
+  a.sel = h->sq_sel;
+  a.hist = h->sq_hist;
+  a.inside = h->sq_inside;
+  a.quant = quant;
+  a.conc = conc;
+  tbeg(h, SPA_T_SUMMARY);
+  SPA_CK(h, launch_weighted_summaries(a, h->stream));
+  tend(h);
+  return SPA_OK;
+}
+
+// Per-scale summaries of the current particles into row `row` of the paths, and the
+// history copy used by the c-marginal mixture.
+spa_status record_summaries(spa_smc *h, int row) {
+  if (!h->sq_on) return SPA_OK;
+  const int L = h->sq_lv.L, D = h->sq_lv.D, p = h->p;
+  spa_status st = run_summaries(h, h->beta, h->f64, h->N, p, h->logw, true, h->sq_lv,
+                                L ? h->quant_path + (size_t)row * L * p : nullptr,
+                                D ? h->conc_path + (size_t)row * D * p : nullptr);
+  if (st != SPA_OK) return st;
+  if (h->sq_keep) {
+    const size_t rb = h->psz * (size_t)h->N * p;
+    SPA_CK(h, hipMemcpyAsync(static_cast<char *>(h->hist_beta) + rb * row, h->beta, rb, hipMemcpyDeviceToDevice,
+                             h->stream));
+    SPA_CK(h, hipMemcpyAsync(h->hist_logw + (size_t)row * h->N, h->logw, 8 * (size_t)h->N,
+                             hipMemcpyDeviceToDevice, h->stream));
+  }
+  return SPA_OK;
+}
+
+spa_status parse_levels(spa_smc *h, const double *levels, int32_t L, const double *deltas, int32_t D,
+                        SqLevels *out) {
+  if (L < 0 || D < 0 || L > kSqMaxLevels || D > kSqMaxLevels)
+    return set_err(h, SPA_ERR_ARG, "between 0 and 8 quantile levels and tolerances");
+  if ((L > 0 && !levels) || (D > 0 && !deltas)) return set_err(h, SPA_ERR_ARG, "levels/deltas is NULL");
+  SqLevels lv{};
+  lv.L = L;
+  lv.D = D;
+  for (int l = 0; l < L; ++l) {
+    if (!(levels[l] > 0.0 && levels[l] <= 1.0)) return set_err(h, SPA_ERR_ARG, "quantile levels must lie in (0, 1]");
+    lv.alpha[l] = levels[l];
+  }
+  for (int d = 0; d < D; ++d) {
+    if (!(deltas[d] > 0.0) || !std::isfinite(deltas[d])) return set_err(h, SPA_ERR_ARG, "tolerances must be > 0");
+    lv.delta[d] = deltas[d];
+  }
+  *out = lv;
+  return SPA_OK;
+}
+
 spa_status validate_cfg(const spa_smc_config *c) {
   if (!c) return set_err(nullptr, SPA_ERR_ARG, "cfg is NULL");
   if (c->n < 1 || c->p < 1 || c->N < 1) return set_err(nullptr, SPA_ERR_SHAPE, "n, p and N must be >= 1");
@@ -665,6 +780,7 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   long long cnt = 0;
   if ((st = read_count(h, &cnt)) != SPA_OK) return st;
   if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
+  if ((st = record_summaries(h, t_new - 1)) != SPA_OK) return st;
   const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (static_cast<double>(h->N) * h->sweeps) : NAN;
   if (h->sweeps > 0) adapt_step(h, acc_rate);
   h->log_z += L;
@@ -775,6 +891,95 @@ extern "C" spa_status spa_smc_resample(spa_smc *h, const double *w_dev, int32_t 
   SPA_CK(h, hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   SPA_CK(h, hipStreamSynchronize(h->stream));
   if (h->hscal[5] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "weights must be finite, >= 0 and not all zero");
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_weighted_summaries(spa_smc *h, const void *values_dev, int32_t M, int32_t p,
+                                             int32_t values_are_fp64, const double *w_dev, const double *levels,
+                                             int32_t L, const double *deltas, int32_t D, double *quant_dev,
+                                             double *conc_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!values_dev || !w_dev) return set_err(h, SPA_ERR_ARG, "values/weights is NULL");
+  if (M < 1 || p < 1) return set_err(h, SPA_ERR_SHAPE, "M and p must be >= 1");
+  SqLevels lv;
+  spa_status st = parse_levels(h, levels, L, deltas, D, &lv);
+  if (st != SPA_OK) return st;
+  if ((L > 0 && !quant_dev) || (D > 0 && !conc_dev)) return set_err(h, SPA_ERR_ARG, "output is NULL");
+  if ((st = run_summaries(h, values_dev, values_are_fp64 != 0, M, p, w_dev, false, lv, quant_dev, conc_dev)) !=
+      SPA_OK)
+    return st;
+  SPA_CK(h, hipMemcpyAsync(h->hscal + 8, &h->sq_st->flags, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  int flags = 0;
+  std::memcpy(&flags, h->hscal + 8, sizeof(int));
+  if (flags & 1) return set_err(h, SPA_ERR_NUMERIC, "weights must be finite, >= 0 and not all zero");
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_set_summaries(spa_smc *h, const double *levels, int32_t L, const double *deltas,
+                                            int32_t D, int32_t keep_history) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (h->t < 1) return set_err(h, SPA_ERR_STATE, "handle not initialised");
+  if (h->sq_on) return set_err(h, SPA_ERR_STATE, "summaries already configured");
+  if (keep_history && h->t != 1) return set_err(h, SPA_ERR_STATE, "the history must start at the first scale");
+  SqLevels lv;
+  spa_status st = parse_levels(h, levels, L, deltas, D, &lv);
+  if (st != SPA_OK) return st;
+  const size_t T = h->T, p = h->p, N = h->N;
+  if (L && (st = dalloc(h, &h->quant_path, 8 * T * L * p)) != SPA_OK) return st;
+  if (D && (st = dalloc(h, &h->conc_path, 8 * T * D * p)) != SPA_OK) return st;
+  if (keep_history) {
+    if ((st = dalloc(h, &h->hist_beta, h->psz * T * N * p)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->hist_logw, 8 * T * N)) != SPA_OK) return st;
+  }
+  h->sq_lv = lv;
+  h->sq_on = true;
+  h->sq_keep = keep_history != 0;
+  for (int row = 0; row < h->t; ++row) {   // the current scale (rows before it are not kept)
+    if (row != h->t - 1) continue;
+    if ((st = record_summaries(h, row)) != SPA_OK) return st;
+  }
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get_summaries(const spa_smc *h, const double **quant_path_dev,
+                                            const double **conc_path_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!h->sq_on) return SPA_ERR_STATE;
+  if (quant_path_dev) *quant_path_dev = h->quant_path;
+  if (conc_path_dev) *conc_path_dev = h->conc_path;
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_marginal_summaries(spa_smc *h, double *quant_dev, double *conc_dev,
+                                                 double *scale_post_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!h->sq_on || !h->sq_keep) return set_err(h, SPA_ERR_STATE, "no particle history (spa_smc_set_summaries)");
+  const SqLevels &lv = h->sq_lv;
+  if ((lv.L > 0 && !quant_dev) || (lv.D > 0 && !conc_dev)) return set_err(h, SPA_ERR_ARG, "output is NULL");
+  const int T = h->t, N = h->N;
+  const size_t M = (size_t)T * N;
+  if (M > 0x7fffffff) return set_err(h, SPA_ERR_SHAPE, "history too large");
+  spa_status st;
+  if (h->sq_w_cap < M) {
+    dfree(h, h->sq_w);
+    h->sq_w = nullptr;
+    if ((st = dalloc(h, &h->sq_w, 8 * M)) != SPA_OK) return st;
+    h->sq_w_cap = M;
+  }
+  if (!h->sq_logz && (st = dalloc(h, &h->sq_logz, 8 * (size_t)h->T)) != SPA_OK) return st;
+  SPA_CK(h, hipMemcpyAsync(h->sq_logz, h->logz_path.data(), 8 * (size_t)T, hipMemcpyHostToDevice, h->stream));
+  tbeg(h, SPA_T_SUMMARY);
+  SPA_CK(h, launch_mixture_weights(h->sq_logz, T, N, h->hist_logw, h->sq_w, scale_post_dev, h->stream));
+  tend(h);
+  if ((st = run_summaries(h, h->hist_beta, h->f64, static_cast<int>(M), h->p, h->sq_w, false, lv, quant_dev,
+                          conc_dev)) != SPA_OK)
+    return st;
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
   return SPA_OK;
 }
 

@@ -117,6 +117,10 @@ def test_null_handle_calls(lib):
     assert lib.spa_smc_resample(None, None, 1, 0, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_set_state(None, None, None, 1, 1.0) == binding.SPA_ERR_ARG
     assert lib.spa_philox4x32_10(None, None, 1, 0, None) == binding.SPA_ERR_ARG
+    assert lib.spa_weighted_summaries(None, None, 1, 1, 0, None, None, 0, None, 0, None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_set_summaries(None, None, 0, None, 0, 0) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_get_summaries(None, None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_marginal_summaries(None, None, None, None) == binding.SPA_ERR_ARG
     lib.spa_smc_destroy(None)
 
 
