@@ -16,7 +16,10 @@ sweep s, (t << 4) | tag), t = 0 for the burn-in sweeps and t >= 1 for the scale 
          pairs (w0, w1) and (w2, w3): r = sqrt(-2 ln((w_even + 1) 2^-32)),
          theta = 2 pi w_odd 2^-32, normals (r cos theta, r sin theta);
   tag 1: MH uniform u = (w0 + 1/2) 2^-32, block 0;
-  tag 2: systematic-resampling offset U = w0 2^-32 at counter (0, 0, 0, (t << 4) | 2).
+  tag 2: systematic-resampling offset U = w0 2^-32 at counter (0, 0, 0, (t << 4) | 2);
+  tag 3: single-site moves: counter (particle i, coordinate j, cycle s, (t << 4) | 3)
+         gives the proposal normal r cos theta from (w0, w1) as above and the MH
+         uniform u = (w2 + 1/2) 2^-32.
 """
 from __future__ import annotations
 
@@ -31,6 +34,7 @@ MASK32 = np.uint64(0xFFFFFFFF)
 TAG_NORMAL = 0
 TAG_UNIFORM = 1
 TAG_RESAMPLE = 2
+TAG_SINGLE = 3
 
 
 def philox4x32_10(ctr, key):
@@ -92,3 +96,17 @@ def resample_u32(seed: int, t: int) -> int:
     """The 32-bit word from which the systematic-resampling offset of scale t is made."""
     ctr = np.array([0, 0, 0, word3(t, TAG_RESAMPLE)], dtype=np.uint64)
     return int(philox4x32_10(ctr, key_of(seed))[0])
+
+
+def single_site_draws(seed: int, N: int, p: int, cycle: int, t: int):
+    """(N, p) proposal normals and (N, p) MH uniforms of one single-site cycle (tag 3)."""
+    ctr = np.zeros((N, p, 4), dtype=np.uint64)
+    ctr[..., 0] = np.arange(N, dtype=np.uint64)[:, None]
+    ctr[..., 1] = np.arange(p, dtype=np.uint64)[None, :]
+    ctr[..., 2] = np.uint64(cycle)
+    ctr[..., 3] = np.uint64(word3(t, TAG_SINGLE))
+    w = philox4x32_10(ctr, key_of(seed)).astype(np.float64)
+    two32 = 2.0 ** -32
+    z = np.sqrt(-2.0 * np.log((w[..., 0] + 1.0) * two32)) * np.cos(2.0 * np.pi * (w[..., 1] * two32))
+    u = (w[..., 2] + 0.5) * two32
+    return z, u

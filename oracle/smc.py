@@ -18,6 +18,10 @@ Readings taken where the paper is silent (each also listed in the design notes):
 * one "sweep" is one joint p-dimensional proposal and one MH decision per particle;
   K_t is ``sweeps`` sweeps of a random walk (scale kappa * sigma_j) or of MALA with
   diagonal preconditioner M = diag(sigma^2) and step h;
+* the paper's own kernel (Section 4.1, further details): one "sweep" is a cycle over
+  j = 1..p of single-coordinate random-walk MH updates with proposal standard deviation
+  ``step`` (the paper's variance 0.25: step 0.5, kept fixed), the linear predictor being
+  updated incrementally, eta += delta X_std[:, j]; K_t is ``sweeps`` such cycles (5);
 * sigma_j is the weighted standard deviation of the current particles under W_t
   before the moves (floored at 1e-12); the first half of the burn-in uses
   2 / sqrt(n), the inverse square root of the diagonal Fisher information at beta = 0,
@@ -38,7 +42,7 @@ import numpy as np
 
 from . import gt_prior, likelihood, philox
 
-TARGET_ACC = {"rwm": 0.234, "mala": 0.574}
+TARGET_ACC = {"rwm": 0.234, "mala": 0.574, "single": None}   # single-site: fixed variance
 SIGMA_FLOOR = 1e-12
 LOG2 = math.log(2.0)
 
@@ -188,8 +192,41 @@ def mala_sweep(prob: Problem, st: State, lam: float, h: float, sigma, seed: int,
     return int(np.count_nonzero(acc))
 
 
+def single_site_sweep(prob: Problem, st: State, lam: float, step: float, sigma, seed: int,
+                      cycle: int, t: int) -> int:
+    """One cycle of single-coordinate random-walk MH updates, j = 1..p in order, for every
+    particle (Section 4.1): beta'_j = beta_j + step z, accepted iff
+    log u < [l(beta') - l(beta)] + log Gt(beta'_j) - log Gt(beta_j), where the likelihood
+    difference comes from the incrementally updated linear predictor eta = X_std beta.
+    Returns the number of accepted coordinate updates."""
+    N, p = st.beta.shape
+    z, u = philox.single_site_draws(seed, N, p, cycle, t)
+    eta = st.beta @ prob.Xs.T                        # (N, n)
+    acc = 0
+    for j in range(p):
+        x = prob.Xs[:, j]
+        delta = step * z[:, j]
+        eta_p = eta + delta[:, None] * x[None, :]
+        if prob.likelihood_off:
+            dll = np.zeros(N)
+        else:
+            dll = (delta * (prob.y @ x)
+                   - np.sum(likelihood.softplus(eta_p) - likelihood.softplus(eta), axis=1))
+        b, bp = st.beta[:, j], st.beta[:, j] + delta
+        dlp = gt_prior.gt_logpdf(bp, prob.a, lam) - gt_prior.gt_logpdf(b, prob.a, lam)
+        ok = np.log(u[:, j]) < dll + dlp
+        st.beta[ok, j] = bp[ok]
+        eta[ok] = eta_p[ok]
+        acc += int(np.count_nonzero(ok))
+    st.ll = prob.loglik(st.beta)
+    return acc
+
+
 def adapt_step(step: float, acc_rate: float, move: str) -> float:
-    """log step += clip(acceptance - target, -log 2, log 2)."""
+    """log step += clip(acceptance - target, -log 2, log 2); the single-site kernel keeps
+    its proposal variance fixed."""
+    if TARGET_ACC[move] is None:
+        return step
     d = min(max(acc_rate - TARGET_ACC[move], -LOG2), LOG2)
     return step * math.exp(d)
 
@@ -218,7 +255,8 @@ def run_smc(prob: Problem, lambdas, N: int, move: str, sweeps: int, init_sweeps:
     n, p = prob.Xs.shape
     if move not in TARGET_ACC:
         raise ValueError(move)
-    sweep_fn = rwm_sweep if move == "rwm" else mala_sweep
+    sweep_fn = {"rwm": rwm_sweep, "mala": mala_sweep, "single": single_site_sweep}[move]
+    upd = N * (p if move == "single" else 1)         # MH decisions per sweep
 
     beta = np.zeros((N, p))
     if move == "mala":
@@ -235,7 +273,7 @@ def run_smc(prob: Problem, lambdas, N: int, move: str, sweeps: int, init_sweeps:
             sigma = _preconditioner(st)
         acc = sweep_fn(prob, st, lam[0], step, sigma, seed, s, 0)
         if adapt:
-            step = adapt_step(step, acc / N, move)
+            step = adapt_step(step, acc / upd, move)
 
     out = Result(lambdas=lam[:T], mean=np.zeros((T, p)), var=np.zeros((T, p)),
                  ess=np.zeros(T), resampled=np.zeros(T, bool), log_z_inc=np.zeros(T),
@@ -265,10 +303,10 @@ def run_smc(prob: Problem, lambdas, N: int, move: str, sweeps: int, init_sweeps:
         acc = 0
         for s in range(sweeps):
             acc += sweep_fn(prob, st, lam[ti], step, sigma, seed, s, t)
-        out.accept[ti] = acc / (N * sweeps)
+        out.accept[ti] = acc / (upd * sweeps)
         out.step[ti] = step
         if adapt:
-            step = adapt_step(step, acc / (N * sweeps), move)
+            step = adapt_step(step, acc / (upd * sweeps), move)
         out.mean[ti], out.var[ti] = weighted_moments(st.beta, st.logW)
         if t in snapshot_at:
             out.snapshots[t] = _snap(st)

@@ -48,9 +48,12 @@ class WorkloadConfig:
 
     def step0(self) -> float:
         """Initial proposal scale: 2.38/sqrt(p) for the random walk, 1.65^2/p^(1/3) for MALA
-        (optimal-scaling constants of Roberts, Gelman & Gilks 1997 and Roberts & Rosenthal 1998)."""
+        (optimal-scaling constants of Roberts, Gelman & Gilks 1997 and Roberts & Rosenthal 1998);
+        0.5 for the single-coordinate kernel (the proposal variance 0.25 of Section 4.1)."""
         if self.move == "rwm":
             return 2.38 / math.sqrt(self.p)
+        if self.move == "single":
+            return 0.5                      # single-coordinate random walk, variance 0.25
         return 1.65 ** 2 / self.p ** (1.0 / 3.0)
 
     def replace(self, **kw) -> "WorkloadConfig":
@@ -85,14 +88,15 @@ CONFIGS = {
     "cfg3_rwm32": WorkloadConfig("cfg3_rwm32", n=5000, p=200, rho=0.97, block=20, k_causal=5,
                                  beta_sd=0.2, N=16384, T=100, a=1.0, move="rwm", sweeps=10,
                                  init_sweeps=500, prec="fp32", seed=3, data_seed=3),
-    # the paper's own shapes (Section 4.1): context runs on synthetic LD genotypes
+    # the paper's own shapes and kernel (Section 4.1: 5 cycles of single-coordinate random-walk
+    # updates per scale): context runs on synthetic LD genotypes
     "paper_small": WorkloadConfig("paper_small", n=500, p=50, rho=0.95, block=0, k_causal=5,
-                                  beta_sd=math.sqrt(0.2), N=8192, T=450, a=1.0, move="rwm",
+                                  beta_sd=math.sqrt(0.2), N=8192, T=450, a=1.0, move="single",
                                   sweeps=5, init_sweeps=200, prec="fp32", ess_frac=0.75,
                                   seed=5, data_seed=5,
                                   lambdas=tuple(2.0 * 0.98 ** np.arange(450))),
     "paper_large": WorkloadConfig("paper_large", n=1859, p=184, rho=0.95, block=0, k_causal=5,
-                                  beta_sd=math.sqrt(0.2), N=8192, T=250, a=4.0, move="rwm",
+                                  beta_sd=math.sqrt(0.2), N=8192, T=250, a=4.0, move="single",
                                   sweeps=5, init_sweeps=200, prec="fp32", ess_frac=0.75,
                                   seed=6, data_seed=6,
                                   # the paper indexes on b = a*c; the sampler's scale is c = b/a

@@ -53,13 +53,13 @@ def _tiny_dataset(p, seed):
     return Xs, d.y.astype(np.float64)
 
 
-@pytest.mark.parametrize("p,move", [(1, "rwm"), (2, "rwm"), (2, "mala")])
+@pytest.mark.parametrize("p,move", [(1, "rwm"), (2, "rwm"), (2, "mala"), (1, "single"), (2, "single")])
 def test_small_p_against_quadrature(p, move):
     Xs, y = _tiny_dataset(p, seed=10 + p)
     a, T, N, R = 1.0, 12, 2000, 6
     lam = lambda_grid(1e3, 1e-2, T)
     prob = smc.Problem(Xs=Xs, y=y, a=a)
-    step0 = 2.38 / math.sqrt(p) if move == "rwm" else 1.65 ** 2 / p ** (1 / 3)
+    step0 = {"rwm": 2.38 / math.sqrt(p), "mala": 1.65 ** 2 / p ** (1 / 3), "single": 0.5}[move]
     runs = [smc.run_smc(prob, lam, N, move, sweeps=5, init_sweeps=150, ess_frac=0.5,
                         step0=step0, seed=100 + r) for r in range(R)]
     means = np.stack([r.mean for r in runs])           # (R, T, p)
@@ -105,6 +105,61 @@ def test_fixed_scale_mcmc_agrees_with_smc():
     se = np.sqrt(smc_means.var(0, ddof=1) / 3 + mc_means.var(0, ddof=1) / 3)
     sd = np.sqrt(smc.weighted_moments(st.beta, st.logW)[1])
     assert np.all(np.abs(diff) <= 6 * se + 0.1 * sd + 2e-3), (diff, se, sd)
+
+
+def test_single_site_increment_is_the_likelihood_difference():
+    """The incremental eta update gives l(beta') - l(beta) of the full likelihood, and an
+    accepted coordinate update changes only that coordinate."""
+    Xs, y = _tiny_dataset(5, seed=3)
+    prob = smc.Problem(Xs=Xs, y=y, a=1.0)
+    rng = np.random.default_rng(0)
+    N = 64
+    beta = rng.normal(0, 0.3, size=(N, 5))
+    st = smc.State(beta=beta.copy(), ll=prob.loglik(beta), gl=np.zeros_like(beta),
+                   logW=np.full(N, -math.log(N)))
+    acc = smc.single_site_sweep(prob, st, 0.5, 0.5, None, seed=7, cycle=0, t=3)
+    # replay the cycle with full likelihood evaluations
+    z, u = smc.philox.single_site_draws(7, N, 5, 0, 3)
+    b = beta.copy()
+    n_acc = 0
+    for j in range(5):
+        bp = b.copy()
+        bp[:, j] += 0.5 * z[:, j]
+        la = (prob.loglik(bp) - prob.loglik(b) + gt_prior.gt_logpdf(bp[:, j], 1.0, 0.5)
+              - gt_prior.gt_logpdf(b[:, j], 1.0, 0.5))
+        ok = np.log(u[:, j]) < la
+        b[ok] = bp[ok]
+        n_acc += int(ok.sum())
+    assert n_acc == acc
+    assert np.allclose(st.beta, b, rtol=0, atol=1e-14)
+    assert np.allclose(st.ll, prob.loglik(b), rtol=1e-13)
+
+
+def test_single_site_prior_only_targets_are_gt():
+    # scales within reach of the fixed 0.5 proposal (a heavy-tailed Gt(1, 1) target needs
+    # far longer random-walk runs than a test affords)
+    a, N, p, T = 4.0, 4096, 2, 6
+    lam = lambda_grid(0.3, 0.03, T)
+    prob = smc.Problem(Xs=np.zeros((10, p)), y=np.zeros(10), a=a, likelihood_off=True)
+    res = smc.run_smc(prob, lam, N, "single", sweeps=20, init_sweeps=200, ess_frac=0.5,
+                      step0=0.5, seed=22, snapshot_at=range(1, T + 1))
+    for t in range(1, T + 1):
+        st = res.snapshots[t]
+        D = weighted_ks(st.beta.ravel(), np.repeat(np.exp(st.logW), p),
+                        lambda v: gt_prior.gt_cdf(v, a, lam[t - 1]))
+        assert D < 0.03, (t, D)
+
+
+def test_single_site_draws_are_the_stream():
+    from oracle import philox
+    z, u = philox.single_site_draws(5, 3, 4, 2, 7)
+    w = philox.philox4x32_10(np.array([[1, 2, 2, (7 << 4) | 3]], dtype=np.uint64), philox.key_of(5))[0]
+    assert u[1, 2] == (float(w[2]) + 0.5) * 2.0 ** -32
+    r = math.sqrt(-2.0 * math.log((float(w[0]) + 1.0) * 2.0 ** -32))
+    assert math.isclose(z[1, 2], r * math.cos(2.0 * math.pi * float(w[1]) * 2.0 ** -32), rel_tol=1e-15)
+    zz, uu = philox.single_site_draws(9, 2000, 50, 0, 1)
+    assert abs(zz.mean()) < 0.01 and abs(zz.var() - 1.0) < 0.01
+    assert abs(uu.mean() - 0.5) < 0.005 and uu.min() > 0.0 and uu.max() < 1.0
 
 
 # ----------------------------------------------------------- planted mistakes
