@@ -63,7 +63,10 @@ typedef enum {
  * SPA_X_AUTO selects BF16. */
 typedef enum { SPA_X_AUTO = 0, SPA_X_FP8E4M3 = 1, SPA_X_BF16 = 2 } spa_xfmt;
 
-typedef enum { SPA_MOVE_RWM = 0, SPA_MOVE_MALA = 1 } spa_move;
+/* Move kernels: joint random walk, preconditioned MALA, or the paper's cycles of
+ * single-coordinate random-walk updates (Section 4.1; one "sweep" = one cycle over the
+ * p coordinates, proposal standard deviation `step0` kept fixed; n <= 2048). */
+typedef enum { SPA_MOVE_RWM = 0, SPA_MOVE_MALA = 1, SPA_MOVE_SINGLE = 2 } spa_move;
 
 typedef struct {
   int32_t n, p, N;        /* individuals, markers, particles; n, p, N >= 1, p <= 511     */
@@ -227,6 +230,10 @@ spa_status spa_smc_marginal_summaries(spa_smc *h, double *quant_dev, double *con
 spa_status spa_smc_get(const spa_smc *h, const void **beta_dev, const double **logw_dev,
                        const double **mean_path_dev, const double **var_path_dev,
                        const double **logz_path_host, int32_t *t_out);
+
+/* Borrow the per-particle log-likelihoods of the current particles (N doubles, device;
+ * valid until the next call that mutates the handle). */
+spa_status spa_smc_get_loglik(const spa_smc *h, const double **loglik_dev);
 
 /* Statistics of scale t (1 <= t <= current t) recorded by init/step. */
 spa_status spa_smc_get_stats(const spa_smc *h, int32_t t, spa_smc_stats *out);

@@ -23,13 +23,14 @@ STATUS_NAMES = ["SPA_OK", "SPA_ERR_ARG", "SPA_ERR_SHAPE", "SPA_ERR_ALLOC", "SPA_
                 "SPA_ERR_STATE", "SPA_ERR_NUMERIC"]
 PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
 XFMT = {"auto": 0, "fp8": 1, "bf16": 2}
-MOVE = {"rwm": 0, "mala": 1}
+MOVE = {"rwm": 0, "mala": 1, "single": 2}
 
 # The exported C entry points (kept in step with include/spa_smc.h).
 EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "spa_smc_resample",
            "spa_weighted_summaries", "spa_smc_set_summaries", "spa_smc_get_summaries",
            "spa_smc_marginal_summaries",
-           "spa_smc_get", "spa_smc_get_stats", "spa_smc_set_state", "spa_philox4x32_10",
+           "spa_smc_get", "spa_smc_get_loglik", "spa_smc_get_stats", "spa_smc_set_state",
+           "spa_philox4x32_10",
            "spa_smc_set_timing", "spa_smc_get_timing", "spa_smc_destroy", "spa_smc_last_error"]
 TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments",
                   "finalize", "summary"]
@@ -89,6 +90,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spa_smc_marginal_summaries.argtypes = [vp, vp, vp, vp]
     lib.spa_smc_get.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
+    lib.spa_smc_get_loglik.argtypes = [vp, ctypes.POINTER(vp)]
     lib.spa_smc_get_stats.argtypes = [vp, i32, ctypes.POINTER(_Stats)]
     lib.spa_smc_set_state.argtypes = [vp, vp, vp, i32, dbl]
     lib.spa_philox4x32_10.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
@@ -242,6 +244,13 @@ class SpaSMC:
         beta = self._copy_dev(b, self.cfg.N * self.cfg.p, self.particle_dtype).view(self.cfg.N, self.cfg.p)
         logw = self._copy_dev(lw, self.cfg.N, torch.float64)
         return beta, logw
+
+    def state_loglik(self):
+        """Log-likelihoods of the current particles (N,) as a new device tensor."""
+        torch = _torch()
+        ll = ctypes.c_void_p()
+        self._check(self.lib.spa_smc_get_loglik(self.h, ctypes.byref(ll)))
+        return self._copy_dev(ll, self.cfg.N, torch.float64)
 
     def paths(self):
         """Per-scale weighted mean and variance (t x p) and cumulative log Z (t,), on the host."""

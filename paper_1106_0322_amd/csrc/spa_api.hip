@@ -12,6 +12,7 @@
 #include "../../include/spa_smc.h"
 #include "spa_internal.hpp"
 #include "spa_kernels.hpp"
+#include "spa_single.hpp"
 #include "spa_summary.hpp"
 
 using namespace spa;
@@ -115,6 +116,8 @@ struct spa_smc {
   std::vector<int> ev_cat;         // category of each recorded pair
   double t_ms[SPA_TIMING_CLASSES] = {0};
   long long t_cnt[SPA_TIMING_CLASSES] = {0};
+  // single-coordinate kernel operands (standardised genotype columns, labels)
+  void *xs_ss = nullptr, *yv_ss = nullptr;
   // sparsity-path summaries (per scale, and the c-marginal mixture)
   SqLevels sq_lv{};
   bool sq_on = false, sq_keep = false;
@@ -432,7 +435,7 @@ spa_status read_count(spa_smc *h, long long *out) {
 }
 
 void adapt_step(spa_smc *h, double acc_rate) {
-  if (!h->adapt) return;
+  if (!h->adapt || h->move == SPA_MOVE_SINGLE) return;   // the single-coordinate variance is fixed
   const double target = h->move == SPA_MOVE_MALA ? 0.574 : 0.234;
   double d = acc_rate - target;
   const double l2 = std::log(2.0);
@@ -446,6 +449,31 @@ spa_status record_moments(spa_smc *h, int row) {
                  h->var_path + (size_t)row * h->p, nullptr, kSigmaFloor, h->stream);
   tend(h);
   SPA_CK(h, hipGetLastError());
+  return SPA_OK;
+}
+
+// Cycles of the single-coordinate kernel (Section 4.1) at scale lam, Philox index t.
+spa_status single_site_cycles(spa_smc *h, int t, int cycles, double lam) {
+  SingleSiteArgs a{};
+  a.xs = h->xs_ss;
+  a.yv = h->yv_ss;
+  a.beta = h->beta;
+  a.ll = h->ll;
+  a.acc_cnt = h->acc;
+  a.prior = make_prior(h, lam);
+  a.step = h->step;
+  a.M = h->N;
+  a.n = h->n;
+  a.n_pad = h->n_pad;
+  a.p = h->p;
+  a.cycles = cycles;
+  a.cycle0 = 0;
+  a.k0 = h->k0;
+  a.k1 = h->k1;
+  a.t = t;
+  tbeg(h, SPA_T_PROPOSE);
+  SPA_CK(h, launch_single_site(h->f64, a, h->stream));
+  tend(h);
   return SPA_OK;
 }
 
@@ -560,7 +588,10 @@ spa_status validate_cfg(const spa_smc_config *c) {
     if (i && !(c->lambda[i] < c->lambda[i - 1]))
       return set_err(nullptr, SPA_ERR_ARG, "lambda must be strictly decreasing");
   }
-  if (c->move != SPA_MOVE_RWM && c->move != SPA_MOVE_MALA) return set_err(nullptr, SPA_ERR_ARG, "bad move");
+  if (c->move != SPA_MOVE_RWM && c->move != SPA_MOVE_MALA && c->move != SPA_MOVE_SINGLE)
+    return set_err(nullptr, SPA_ERR_ARG, "bad move");
+  if (c->move == SPA_MOVE_SINGLE && c->n > single_site_max_n())
+    return set_err(nullptr, SPA_ERR_SHAPE, "the single-coordinate kernel holds at most 2048 individuals");
   if (c->sweeps < 0 || c->init_sweeps < 0) return set_err(nullptr, SPA_ERR_ARG, "sweeps must be >= 0");
   if (!(c->ess_frac > 0.0 && c->ess_frac <= 1.0)) return set_err(nullptr, SPA_ERR_ARG, "ess_frac in (0, 1]");
   if (!(c->step0 > 0.0) || !std::isfinite(c->step0)) return set_err(nullptr, SPA_ERR_ARG, "step0 must be > 0");
@@ -686,12 +717,26 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   }
   launch_col_stats(h->dX, h->dy, n, p, h->mu, h->s, h->inv_s, h->ytil, h->dbad, h->stream);
   if ((st = ensure_xpack(h, h->prec)) != SPA_OK) return fail(st);
+  if (h->move == SPA_MOVE_SINGLE) {
+    if ((st = dalloc(h, &h->xs_ss, h->psz * (size_t)p * h->n_pad)) != SPA_OK) return fail(st);
+    if ((st = dalloc(h, &h->yv_ss, h->psz * (size_t)h->n_pad)) != SPA_OK) return fail(st);
+    he = launch_std_cols(h->f64, h->dX, n, p, h->n_pad, h->mu, h->s, h->xs_ss, h->stream);
+    if (he != hipSuccess) {
+      hip_fail(h, he, "std_cols");
+      return fail(SPA_ERR_HIP);
+    }
+    launch_labels(h->dy, n, h->n_pad, h->f64, h->yv_ss, h->stream);
+  }
 
   // ---- initial particles: beta = 0, burn-in targeting pi_1, equal weights
   launch_fill(h->logw, h->N, -std::log(static_cast<double>(h->N)), h->stream);
   launch_fill(h->sigma, p, 2.0 / std::sqrt(static_cast<double>(n)), h->stream);
   if ((st = eval_state(h, h->beta, h->ll, h->gl)) != SPA_OK) return fail(st);
-  for (int s = 0; s < h->init_sweeps; ++s) {
+  if (h->move == SPA_MOVE_SINGLE && h->init_sweeps > 0) {   // one launch: fixed variance, no adaptation
+    launch_zero_int(h->acc, h->N, h->stream);
+    if ((st = single_site_cycles(h, 0, h->init_sweeps, h->lambda[0])) != SPA_OK) return fail(st);
+  }
+  for (int s = 0; s < (h->move == SPA_MOVE_SINGLE ? 0 : h->init_sweeps); ++s) {
     if (s == h->init_sweeps / 2) {
       launch_moments(h->f64, h->beta, h->logw, h->N, p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
                      h->stream);
@@ -775,13 +820,18 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   tend(h);
   launch_zero_int(h->acc, h->N, h->stream);
   const double step_used = h->step;
-  for (int s = 0; s < h->sweeps; ++s)
-    if ((st = sweep(h, t_new, s, lam_new)) != SPA_OK) return st;
+  if (h->move == SPA_MOVE_SINGLE) {
+    if (h->sweeps > 0 && (st = single_site_cycles(h, t_new, h->sweeps, lam_new)) != SPA_OK) return st;
+  } else {
+    for (int s = 0; s < h->sweeps; ++s)
+      if ((st = sweep(h, t_new, s, lam_new)) != SPA_OK) return st;
+  }
   long long cnt = 0;
   if ((st = read_count(h, &cnt)) != SPA_OK) return st;
   if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_summaries(h, t_new - 1)) != SPA_OK) return st;
-  const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (static_cast<double>(h->N) * h->sweeps) : NAN;
+  const double upd = static_cast<double>(h->N) * (h->move == SPA_MOVE_SINGLE ? h->p : 1);   // MH decisions per sweep
+  const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (upd * h->sweeps) : NAN;
   if (h->sweeps > 0) adapt_step(h, acc_rate);
   h->log_z += L;
   h->t = t_new;
@@ -993,6 +1043,12 @@ extern "C" spa_status spa_smc_get(const spa_smc *h, const void **beta_dev, const
   if (var_path_dev) *var_path_dev = h->var_path;
   if (logz_path_host) *logz_path_host = h->logz_path.data();
   if (t_out) *t_out = h->t;
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get_loglik(const spa_smc *h, const double **loglik_dev) {
+  if (!h || !loglik_dev) return set_err(const_cast<spa_smc *>(h), SPA_ERR_ARG, "NULL argument");
+  *loglik_dev = h->ll;
   return SPA_OK;
 }
 

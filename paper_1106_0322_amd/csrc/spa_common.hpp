@@ -35,7 +35,7 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 }
 
 // Stream layout: counter = (particle, block, sweep, (t << 4) | tag).
-enum : uint32_t { kTagNormal = 0, kTagUniform = 1, kTagResample = 2 };
+enum : uint32_t { kTagNormal = 0, kTagUniform = 1, kTagResample = 2, kTagSingleSite = 3 };
 
 __device__ __forceinline__ uint32_t word3(int t, uint32_t tag) {
   return (static_cast<uint32_t>(t) << 4) | tag;

@@ -1,0 +1,225 @@
+// The paper's own move kernel (Section 4.1): cycles of single-coordinate random-walk
+// Metropolis-Hastings updates, beta'_j = beta_j + step z for j = 1..p in order, each
+// costing O(n) through the incrementally updated linear predictor eta = X_std beta.
+//
+// One wave64 per particle.  The particle's eta (and e^{-|eta|}) live in registers for
+// the whole launch: lane l holds individuals l, l+64, ..., so an update reads one
+// standardised genotype column (contiguous bytes per lane group), forms the likelihood
+// difference with one exponential per individual (the cached e^{-|eta|} gives the other
+// softplus term) and one logarithm per lane (the ratio terms are multiplied first), and
+// reduces it across the wave.  The particle's coefficients are held by lane j mod 64 and
+// broadcast with readlane; the cycle's normals and uniforms are drawn up front, one
+// Philox block per coordinate, by the lane holding that coordinate.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "spa_common.hpp"
+#include "spa_single.hpp"
+
+namespace spa {
+
+namespace {
+
+constexpr int kMaxCoordBlocks = 8;   // p <= 512
+
+__device__ __forceinline__ float bcast(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-1.4426950408889634f * x); }
+__device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
+__device__ __forceinline__ float log_t(float x) { return __logf(x); }
+__device__ __forceinline__ double log_t(double x) { return log(x); }
+
+// Box-Muller cosine normal from (w0, w1), in the particle precision.
+__device__ __forceinline__ double draw_normal(uint4 w, double) {
+  const double r = sqrt(-2.0 * log((static_cast<double>(w.x) + 1.0) * 0x1p-32));
+  return r * cos(6.283185307179586476925286766559 * (static_cast<double>(w.y) * 0x1p-32));
+}
+__device__ __forceinline__ float draw_normal(uint4 w, float) {
+  const float l = __builtin_amdgcn_logf((static_cast<float>(w.x) + 1.0f) * 0x1p-32f);
+  return __builtin_amdgcn_sqrtf(-1.3862943611198906f * l) * __builtin_amdgcn_cosf(static_cast<float>(w.y) * 0x1p-32f);
+}
+
+template <typename PT, int R>
+__global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= a.M) return;
+  const int n = a.n, n_pad = a.n_pad, p = a.p;
+  const PT *xs = reinterpret_cast<const PT *>(a.xs);   // p x n_pad, zero padded
+  const PT *yv = reinterpret_cast<const PT *>(a.yv);
+  PT *beta = reinterpret_cast<PT *>(a.beta) + (size_t)i * p;
+  const Prior pr = a.prior;
+  const PT step = static_cast<PT>(a.step);
+
+  // coefficients: lane l holds beta_j for j = l + 64 m
+  PT bv[kMaxCoordBlocks];
+#pragma unroll
+  for (int m = 0; m < kMaxCoordBlocks; ++m) {
+    const int j = lane + 64 * m;
+    bv[m] = j < p ? beta[j] : PT(0);
+  }
+  // linear predictor of this particle
+  PT eta[R], em[R], yk[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    eta[r] = PT(0);
+    const int k = lane + 64 * r;
+    yk[r] = k < n_pad ? yv[k] : PT(0);
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxCoordBlocks; ++m) {
+    if (64 * m >= p) break;
+    for (int jl = 0; jl < 64 && 64 * m + jl < p; ++jl) {
+      const int j = 64 * m + jl;
+      const PT bj = bcast(bv[m], jl);
+      const PT *col = xs + (size_t)j * n_pad;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = lane + 64 * r;
+        if (k < n_pad) eta[r] += bj * col[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) em[r] = exp_neg(fabs(eta[r]));
+
+  int cnt = 0;
+  for (int c = 0; c < a.cycles; ++c) {
+    const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
+    PT zv[kMaxCoordBlocks];
+    uint32_t uw[kMaxCoordBlocks];   // MH uniform u = (w2 + 1/2) 2^-32, kept as its word
+#pragma unroll
+    for (int m = 0; m < kMaxCoordBlocks; ++m) {
+      const int j = lane + 64 * m;
+      zv[m] = PT(0);
+      uw[m] = 0u;
+      if (64 * m < p && j < p) {
+        const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j), cyc,
+                                                 word3(a.t, kTagSingleSite)),
+                                      a.k0, a.k1);
+        zv[m] = draw_normal(w, PT(0));
+        uw[m] = w.z;
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < kMaxCoordBlocks; ++m) {
+      if (64 * m >= p) break;
+      for (int jl = 0; jl < 64 && 64 * m + jl < p; ++jl) {
+        const int j = 64 * m + jl;
+        const PT delta = step * bcast(zv[m], jl);
+        const PT *col = xs + (size_t)j * n_pad;
+        PT d[R], en[R];
+        PT prod = PT(1), lin = PT(0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int k = lane + 64 * r;
+          const PT x = k < n_pad ? col[k] : PT(0);
+          d[r] = delta * x;
+          const PT e1 = eta[r] + d[r];
+          en[r] = exp_neg(fabs(e1));
+          // softplus(eta) - softplus(eta + d) = max(eta,0) - max(eta+d,0) + log((1+em)/(1+en))
+          prod *= (PT(1) + em[r]) / (PT(1) + en[r]);
+          lin += yk[r] * d[r] + (fmax(eta[r], PT(0)) - fmax(e1, PT(0)));
+        }
+        const double dll = wave_sum(static_cast<double>(lin + log_t(prod)));
+        const double bj = static_cast<double>(bcast(bv[m], jl));
+        const double bn = static_cast<double>(static_cast<PT>(bj) + delta);
+        const double dlp = gt_logpdf(bn, pr) - gt_logpdf(bj, pr);
+        const uint32_t w2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(uw[m]), jl));
+        const double u = (static_cast<double>(w2) + 0.5) * 0x1p-32;
+        if (log(u) < dll + dlp) {   // uniform across the wave (the sums are lane-identical)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            eta[r] += d[r];
+            em[r] = en[r];
+          }
+          if (lane == jl) bv[m] = static_cast<PT>(bn);
+          ++cnt;
+        }
+      }
+    }
+  }
+
+  // write back: coefficients, log-likelihood from the tracked predictor, accept count
+#pragma unroll
+  for (int m = 0; m < kMaxCoordBlocks; ++m) {
+    const int j = lane + 64 * m;
+    if (j < p) beta[j] = bv[m];
+  }
+  double ll = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int k = lane + 64 * r;
+    if (k < n) {
+      const double e = static_cast<double>(eta[r]);
+      ll += static_cast<double>(yk[r]) * e - (fmax(e, 0.0) + log1p(exp(-fabs(e))));
+    }
+  }
+  ll = wave_sum(ll);
+  if (lane == 0) {
+    a.ll[i] = ll;
+    a.acc_cnt[i] += cnt;
+  }
+}
+
+// Standardised genotype columns for the single-site kernel: xs[j][k] = (X_kj - mu_j) / s_j
+// in the particle precision (rounded once from FP64), zero for padded individuals.
+template <typename PT>
+__global__ void std_cols_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad,
+                                const double *__restrict__ mu, const double *__restrict__ s,
+                                PT *__restrict__ xs) {
+  const size_t total = (size_t)p * n_pad;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = static_cast<int>(idx / n_pad), k = static_cast<int>(idx % n_pad);
+    xs[idx] = k < n ? static_cast<PT>((static_cast<double>(X[(size_t)k * p + j]) - mu[j]) / s[j]) : PT(0);
+  }
+}
+
+template <typename PT, int R>
+static void launch_r(const SingleSiteArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL((single_site_kernel<PT, R>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
+}
+
+template <typename PT>
+static hipError_t launch_t(const SingleSiteArgs &a, hipStream_t st) {
+  const int R = (a.n_pad + 63) / 64;
+  if (R <= 4) launch_r<PT, 4>(a, st);
+  else if (R <= 8) launch_r<PT, 8>(a, st);
+  else if (R <= 16) launch_r<PT, 16>(a, st);
+  else if (R <= 32) launch_r<PT, 32>(a, st);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace
+
+int single_site_max_n() { return 64 * 32; }
+
+hipError_t launch_single_site(bool f64, const SingleSiteArgs &a, hipStream_t st) {
+  if (a.p > 64 * kMaxCoordBlocks) return hipErrorInvalidValue;
+  return f64 ? launch_t<double>(a, st) : launch_t<float>(a, st);
+}
+
+hipError_t launch_std_cols(bool f64, const uint8_t *X, int n, int p, int n_pad, const double *mu,
+                           const double *s, void *xs, hipStream_t st) {
+  const size_t total = (size_t)p * n_pad;
+  const int grid = static_cast<int>((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
+  if (f64)
+    hipLaunchKernelGGL(std_cols_kernel<double>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, mu, s,
+                       reinterpret_cast<double *>(xs));
+  else
+    hipLaunchKernelGGL(std_cols_kernel<float>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, mu, s,
+                       reinterpret_cast<float *>(xs));
+  return hipGetLastError();
+}
+
+}  // namespace spa

@@ -1,0 +1,105 @@
+"""GPU parity of the paper's single-coordinate random-walk kernel (Section 4.1) against
+the FP64 oracle.
+
+* FP64 end to end: the Philox streams are shared, so the GPU trajectory (every accept
+  decision of every coordinate update) tracks the oracle's to round-off;
+* FP32: posterior-mean and log Z paths within Monte Carlo error over independent seeds;
+* the log-likelihood the kernel leaves (from its incrementally updated predictor) equals
+  the likelihood of the particles it leaves."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import likelihood, smc
+from synth import CONFIGS, make_dataset
+from tests.gpu_util import rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _setup(n, p, seed, **over):
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    cfg = CONFIGS["paper_small"].replace(**over)
+    d = make_dataset(cfg, n=n, p=p, seed=seed)
+    sc = SamplerConfig.from_workload(cfg, n=n, p=p)
+    return cfg, d.X, d.y, sc, SpaSMC
+
+
+@pytest.mark.parametrize("n,p,N,T,S,init", [
+    (500, 10, 256, 6, 2, 6),      # one coordinate block, 8 individuals per lane
+    (130, 150, 64, 4, 1, 2),      # three coordinate blocks, padded individuals
+    (2048, 5, 32, 3, 1, 1),       # the largest n the kernel holds in registers
+])
+def test_fp64_trajectory_tracks_oracle(n, p, N, T, S, init):
+    cfg, X, y, sc, SpaSMC = _setup(n, p, seed=n + p, N=N, T=T, sweeps=S, init_sweeps=init,
+                                   prec="fp64", lambdas=tuple(0.5 * 0.8 ** np.arange(T)))
+    Xs, _, _ = likelihood.standardise(X)
+    prob = smc.Problem(Xs=Xs, y=y.astype(np.float64), a=cfg.a)
+    r = smc.run_smc(prob, cfg.grid(), N, "single", S, init, cfg.ess_frac, 0.5, cfg.seed)
+    g = SpaSMC(sc, X, y)
+    print(f"single-site fp64 n={n} p={p} N={N}", flush=True)
+    stats = g.run()
+    mean, var, logz = g.paths()
+    beta, _ = g.particles()
+    d = np.abs(mean - r.mean).max()
+    db = np.abs(beta.cpu().numpy() - r.state.beta).max()
+    print(f"mean path max diff {d:.3e}; particles max diff {db:.3e}")
+    assert d <= 1e-8 and db <= 1e-8
+    assert np.allclose(logz, r.log_z, rtol=1e-10, atol=1e-9)
+    assert [s["resampled"] for s in stats] == list(r.resampled)
+    acc = np.array([s["accept_rate"] for s in stats[1:]])
+    assert np.allclose(acc, r.accept[1:], rtol=0, atol=1e-12)
+
+
+def test_loglik_left_by_the_kernel_is_the_likelihood_of_its_particles():
+    torch = _torch()
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        cfg, X, y, sc, SpaSMC = _setup(500, 50, seed=3, N=512, T=4, sweeps=5, init_sweeps=10, prec=prec)
+        g = SpaSMC(sc, X, y)
+        g.step()
+        beta, _ = g.particles()
+        Xs, _, _ = likelihood.standardise(X)
+        ll_gpu = g.state_loglik().cpu().numpy()
+        ref = likelihood.loglik(beta.double().cpu().numpy(), Xs, y.astype(np.float64))
+        e = rel_err(ll_gpu, ref).max()
+        print(f"{prec}: loglik of the particles, max rel err {e:.3e}")
+        assert e <= tol
+
+
+def test_fp32_statistical_parity():
+    n, p, N, T, S = 500, 12, 512, 8, 2
+    R = 5
+    cfg, X, y, sc, SpaSMC = _setup(n, p, seed=9, N=N, T=T, sweeps=S, init_sweeps=20, prec="fp32",
+                                   lambdas=tuple(1.0 * 0.8 ** np.arange(T)))
+    Xs, _, _ = likelihood.standardise(X)
+    prob = smc.Problem(Xs=Xs, y=y.astype(np.float64), a=cfg.a)
+    gm, om, gz, oz = [], [], [], []
+    for r in range(R):
+        g = SpaSMC(dataclasses.replace(sc, seed=1000 + r), X, y)
+        g.run()
+        m, _, z = g.paths()
+        gm.append(m)
+        gz.append(z)
+        res = smc.run_smc(prob, cfg.grid(), N, "single", S, 20, cfg.ess_frac, 0.5, 2000 + r)
+        om.append(res.mean)
+        oz.append(res.log_z)
+    for name, a, b in (("means", np.array(gm), np.array(om)), ("log Z", np.array(gz), np.array(oz))):
+        va, vb = a.var(0, ddof=1) / R, b.var(0, ddof=1) / R
+        z = (a.mean(0) - b.mean(0)) / np.sqrt(va + vb + 1e-30)
+        print(f"{name}: max|z| {np.abs(z).max():.2f}, frac>3 {np.mean(np.abs(z) > 3):.3f}")
+        assert np.abs(z).max() <= 8 and np.mean(np.abs(z) > 3) <= 0.05
+
+
+def test_rejects_too_many_individuals():
+    from paper_1106_0322_amd import SpaError
+    cfg, X, y, sc, SpaSMC = _setup(2050, 5, seed=1, N=16, T=2, sweeps=1, init_sweeps=0, prec="fp32")
+    with pytest.raises(SpaError) as ei:
+        SpaSMC(sc, X, y)
+    assert ei.value.status == 2
