@@ -69,6 +69,49 @@ def copy_calibration():
     print(f"copied 3 x {n * 4} bytes", flush=True)
 
 
+# VALU issue slots per eta-element update of the FP32 single-coordinate kernel (its ISA:
+# 141 VALU + 17 transcendental instructions per coordinate update of 8 individuals per
+# lane, a transcendental taking four slots), and the chip's VALU lane-slot rate:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 vector peak counts an
+# FMA as two flops and packed FP32 as two lanes).
+SINGLE_SITE_SLOTS = (141 + 4 * 17) / 8.0
+VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+
+
+def single_site_leg(steps: int = 10):
+    """The paper's kernel (Section 4.1) at the paper's small shape: n=500, p=50, N=8192,
+    5 cycles of single-coordinate updates per scale, FP32.  Throughput in eta-element
+    updates per second (5 N p n per scale)."""
+    import torch
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    from synth import CONFIGS, make_dataset
+
+    cfg = CONFIGS["paper_small"]
+    d = make_dataset(cfg)
+    s = SpaSMC(SamplerConfig.from_workload(cfg, init_sweeps=5), d.X, d.y)
+    for _ in range(2):
+        s.step()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    ms_k, cnt = s.timing()["propose"]          # the single-coordinate launches
+    s.close()
+    k_s = ms_k / max(cnt, 1) * 1e-3
+    units = cfg.sweeps * cfg.N * cfg.p * cfg.n
+    rate_k = units / k_s
+    return {"workload": f"n={cfg.n} p={cfg.p} N={cfg.N} a={cfg.a} 5 single-coordinate cycles per scale, fp32",
+            "ms_per_step": round(el * 1e3, 4), "kernel_ms_per_step": round(k_s * 1e3, 4),
+            "eta_updates_per_s": round(units / el, 1), "kernel_eta_updates_per_s": round(rate_k, 1),
+            "est_full_run_s_T450": round(el * (cfg.T - 1), 2),
+            "roofline": {"bound": "alu", "achieved": round(rate_k * SINGLE_SITE_SLOTS / 1e12, 3),
+                         "peak": round(VALU_LANE_SLOTS_PER_S / 1e12, 3), "unit": "T VALU lane-slots/s",
+                         "frac": round(rate_k * SINGLE_SITE_SLOTS / VALU_LANE_SLOTS_PER_S, 4)}}
+
+
 def gemm_flops(cfg) -> float:
     """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
     f = 2.0 * cfg.N * cfg.n * cfg.p
@@ -170,6 +213,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")
     ap.add_argument("--ess-seeds", type=int, default=8)
+    ap.add_argument("--no-single", action="store_true", help="skip the single-coordinate kernel leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference "
                          "launch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -239,6 +283,8 @@ def main():
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
     s.close()
+    if not args.no_single:
+        out["single_site"] = single_site_leg()
     if not args.no_ess:
         out["ess"] = ess_protocol(args.ess_seeds)
     if not args.no_cpu:

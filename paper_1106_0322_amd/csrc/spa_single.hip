@@ -34,8 +34,35 @@ __device__ __forceinline__ double bcast(double v, int lane) {
 
 __device__ __forceinline__ float exp_neg(float x) { return __builtin_amdgcn_exp2f(-1.4426950408889634f * x); }
 __device__ __forceinline__ double exp_neg(double x) { return exp(-x); }
-__device__ __forceinline__ float log_t(float x) { return __logf(x); }
+__device__ __forceinline__ float log_t(float x) { return 0.6931471805599453f * __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double log_t(double x) { return log(x); }
+__device__ __forceinline__ float ratio(float num, float den) { return num * __builtin_amdgcn_rcpf(den); }
+__device__ __forceinline__ double ratio(double num, double den) { return num / den; }
+
+// Lane-identical wave sums (xor butterfly: every lane adds the same pairs, commutatively).
+__device__ __forceinline__ float wave_sum_t(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_t(double v) { return wave_sum(v); }
+
+// log u and log Gt(b') - log Gt(b) in the particle precision (FP64: the oracle's
+// arithmetic, so the decisions match it; FP32: one logarithm of a ratio each).
+__device__ __forceinline__ double log_uniform(uint32_t w, double) {
+  return log((static_cast<double>(w) + 0.5) * 0x1p-32);
+}
+__device__ __forceinline__ float log_uniform(uint32_t w, float) {
+  return log_t((static_cast<float>(w) + 0.5f) * 0x1p-32f);
+}
+__device__ __forceinline__ double prior_diff(double bn, double b, const Prior &pr) {
+  return gt_logpdf(bn, pr) - gt_logpdf(b, pr);
+}
+__device__ __forceinline__ float prior_diff(float bn, float b, const Prior &pr) {
+  if (pr.inf) return -(fabsf(bn) - fabsf(b)) * static_cast<float>(1.0 / pr.lam);
+  const float ac = static_cast<float>(pr.a * pr.lam);
+  return -static_cast<float>(pr.a + 1.0) * log_t(ratio(ac + fabsf(bn), ac + fabsf(b)));
+}
 
 // Box-Muller cosine normal from (w0, w1), in the particle precision.
 __device__ __forceinline__ double draw_normal(uint4 w, double) {
@@ -126,22 +153,21 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
           const PT e1 = eta[r] + d[r];
           en[r] = exp_neg(fabs(e1));
           // softplus(eta) - softplus(eta + d) = max(eta,0) - max(eta+d,0) + log((1+em)/(1+en))
-          prod *= (PT(1) + em[r]) / (PT(1) + en[r]);
+          prod *= ratio(PT(1) + em[r], PT(1) + en[r]);
           lin += yk[r] * d[r] + (fmax(eta[r], PT(0)) - fmax(e1, PT(0)));
         }
-        const double dll = wave_sum(static_cast<double>(lin + log_t(prod)));
-        const double bj = static_cast<double>(bcast(bv[m], jl));
-        const double bn = static_cast<double>(static_cast<PT>(bj) + delta);
-        const double dlp = gt_logpdf(bn, pr) - gt_logpdf(bj, pr);
+        const PT dll = wave_sum_t(lin + log_t(prod));
+        const PT bj = bcast(bv[m], jl);
+        const PT bn = bj + delta;
+        const PT dlp = prior_diff(bn, bj, pr);
         const uint32_t w2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(uw[m]), jl));
-        const double u = (static_cast<double>(w2) + 0.5) * 0x1p-32;
-        if (log(u) < dll + dlp) {   // uniform across the wave (the sums are lane-identical)
+        if (log_uniform(w2, PT(0)) < dll + dlp) {   // uniform across the wave (lane-identical sums)
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             eta[r] += d[r];
             em[r] = en[r];
           }
-          if (lane == jl) bv[m] = static_cast<PT>(bn);
+          if (lane == jl) bv[m] = bn;
           ++cnt;
         }
       }
