@@ -21,6 +21,8 @@ definition it cites:
                     likelihood ratios, systematic resampling, random-walk and MALA moves,
                     weighted moments and the scale-adaptation rule.
 * ``quadrature`` -- brute-force posterior means and log marginal likelihoods for p = 1, 2.
+* ``em``         -- MAP estimates by the EM algorithm of Section 2.1 (weighted-L1 logistic
+                    inner problems by coordinate ascent) and the MAP path of Section 4.1.
 * ``spa``        -- the sparsity-path summaries (Section 5): weighted quantiles (absolute
                     medians, credible intervals), concentrations, the posterior over the
                     scale and the c-marginal mixture (Section 4, eq. all_particles).
@@ -30,4 +32,4 @@ library special cases, invariants, brute force, published known-answer vectors);
 posterior-mean paths at p >= 10 are pinned only statistically (there is no closed
 form), see the test-suite.
 """
-from . import gt_prior, likelihood, philox, smc, quadrature, spa  # noqa: F401
+from . import gt_prior, likelihood, philox, smc, quadrature, spa, em  # noqa: F401
