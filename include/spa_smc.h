@@ -220,6 +220,31 @@ spa_status spa_smc_marginal_summaries(spa_smc *h, double *quant_dev, double *con
                                       double *scale_post_dev);
 
 /*
+ * MAP estimates (Section 2.1): EM on the scale-mixture representation.  E step:
+ * w_j = (a+1)/(a lambda + |beta_j|) (1/lambda for the double exponential); M step: `inner`
+ * sweeps of cyclic coordinate ascent (j = 1..p) of log f(y | X, beta) - sum_j w_j |beta_j|
+ * with the curvature bound n/4: beta_j <- S(beta_j + 4 g_j / n, 4 w_j / n), S the
+ * soft-threshold, g_j the likelihood gradient; `outer` E steps.  FP64 throughout.
+ *
+ * spa_map_em -- from M start points beta0_dev (M x p, FP64 if beta_is_fp64 else FP32) at
+ * scale lambda: mode_dev (M x p doubles) and logpost_dev (M doubles, log f + sum log Gt at
+ * the mode).  Asynchronous on the handle's stream.  Errors: SPA_ERR_ARG, SPA_ERR_SHAPE
+ * (M < 1, n > 10240, p > 512).
+ */
+spa_status spa_map_em(spa_smc *h, const void *beta0_dev, int32_t M, int32_t beta_is_fp64, double lambda,
+                      int32_t outer, int32_t inner, double *mode_dev, double *logpost_dev);
+
+/*
+ * spa_smc_set_map -- record the MAP path (Section 4.1): at the current scale and after the
+ * moves of every later one, EM from the particle of highest posterior density and from
+ * the previous scale's MAP; the mode of higher posterior density is kept (the first on a
+ * tie).  Once per handle.  spa_smc_get_map borrows the T x p path (rows of the scales
+ * recorded) and its T log posterior densities.  Errors: SPA_ERR_STATE, SPA_ERR_SHAPE.
+ */
+spa_status spa_smc_set_map(spa_smc *h, int32_t outer, int32_t inner);
+spa_status spa_smc_get_map(const spa_smc *h, const double **map_path_dev, const double **logpost_path_dev);
+
+/*
  * spa_smc_get -- borrow the current state: particles (N x p, FP64 for SPA_PREC_FP64
  * else FP32), normalised log weights (N doubles), the per-scale weighted mean and
  * variance of every coefficient (T x p doubles each, rows 0..t-1 filled) and the host
@@ -274,7 +299,8 @@ enum {
   SPA_T_MOMENTS = 6,    /* weighted moments                                            */
   SPA_T_FINALIZE = 7,   /* ordered sum of the contraction's split partials             */
   SPA_T_SUMMARY = 8,    /* sparsity-path summaries (quantiles, concentrations)         */
-  SPA_TIMING_CLASSES = 9
+  SPA_T_MAP = 9,        /* EM MAP estimates                                            */
+  SPA_TIMING_CLASSES = 10
 };
 spa_status spa_smc_set_timing(spa_smc *h, int32_t enable);
 spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches);

@@ -28,12 +28,12 @@ MOVE = {"rwm": 0, "mala": 1, "single": 2}
 # The exported C entry points (kept in step with include/spa_smc.h).
 EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "spa_smc_resample",
            "spa_weighted_summaries", "spa_smc_set_summaries", "spa_smc_get_summaries",
-           "spa_smc_marginal_summaries",
+           "spa_smc_marginal_summaries", "spa_map_em", "spa_smc_set_map", "spa_smc_get_map",
            "spa_smc_get", "spa_smc_get_loglik", "spa_smc_get_stats", "spa_smc_set_state",
            "spa_philox4x32_10",
            "spa_smc_set_timing", "spa_smc_get_timing", "spa_smc_destroy", "spa_smc_last_error"]
 TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments",
-                  "finalize", "summary"]
+                  "finalize", "summary", "map"]
 
 
 class SpaError(RuntimeError):
@@ -91,6 +91,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spa_smc_get.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                 ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32)]
     lib.spa_smc_get_loglik.argtypes = [vp, ctypes.POINTER(vp)]
+    lib.spa_map_em.argtypes = [vp, vp, i32, i32, dbl, i32, i32, vp, vp]
+    lib.spa_smc_set_map.argtypes = [vp, i32, i32]
+    lib.spa_smc_get_map.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp)]
     lib.spa_smc_get_stats.argtypes = [vp, i32, ctypes.POINTER(_Stats)]
     lib.spa_smc_set_state.argtypes = [vp, vp, vp, i32, dbl]
     lib.spa_philox4x32_10.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
@@ -356,6 +359,35 @@ class SpaSMC:
         self._check(self.lib.spa_smc_marginal_summaries(self.h, _ptr(q) if L else None, _ptr(c) if D else None,
                                                         _ptr(sp)))
         return q.cpu().numpy(), c.cpu().numpy(), sp.cpu().numpy()
+
+    # ---------------------------------------------------------------- MAP estimates
+    def map_em(self, beta0, lam: float, outer: int = 50, inner: int = 5):
+        """EM modes (M x p, FP64) and their log posterior densities from start points beta0."""
+        torch = _torch()
+        beta0 = beta0.to(self.device).contiguous()
+        if beta0.dim() == 1:
+            beta0 = beta0[None, :]
+        assert beta0.dtype in (torch.float32, torch.float64) and beta0.shape[1] == self.cfg.p
+        mode = torch.empty(beta0.shape, dtype=torch.float64, device=self.device)
+        lp = torch.empty(beta0.shape[0], dtype=torch.float64, device=self.device)
+        self._check(self.lib.spa_map_em(self.h, _ptr(beta0), beta0.shape[0], int(beta0.dtype == torch.float64),
+                                        float(lam), int(outer), int(inner), _ptr(mode), _ptr(lp)))
+        return mode, lp
+
+    def set_map(self, outer: int = 50, inner: int = 5):
+        self._check(self.lib.spa_smc_set_map(self.h, int(outer), int(inner)))
+
+    def map_path(self):
+        """MAP path (t x p) and its log posterior densities (t,), on the host."""
+        torch = _torch()
+        mp, lp = ctypes.c_void_p(), ctypes.c_void_p()
+        self._check(self.lib.spa_smc_get_map(self.h, ctypes.byref(mp), ctypes.byref(lp)))
+        _, _, _, _, _, t = self._get()
+        T, p = len(self._lam), self.cfg.p
+        m = self._copy_dev(mp, T * p, torch.float64).view(T, p)
+        v = self._copy_dev(lp, T, torch.float64)
+        self.stream.synchronize()
+        return m[:t].cpu().numpy(), v[:t].cpu().numpy()
 
     def set_timing(self, enable: bool = True):
         self._check(self.lib.spa_smc_set_timing(self.h, int(bool(enable))))

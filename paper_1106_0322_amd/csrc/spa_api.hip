@@ -12,6 +12,7 @@
 #include "../../include/spa_smc.h"
 #include "spa_internal.hpp"
 #include "spa_kernels.hpp"
+#include "spa_map.hpp"
 #include "spa_single.hpp"
 #include "spa_summary.hpp"
 
@@ -116,6 +117,13 @@ struct spa_smc {
   std::vector<int> ev_cat;         // category of each recorded pair
   double t_ms[SPA_TIMING_CLASSES] = {0};
   long long t_cnt[SPA_TIMING_CLASSES] = {0};
+  // EM MAP estimates (FP64 standardised columns and labels) and the MAP path
+  double *map_xs = nullptr, *map_yv = nullptr;
+  bool map_on = false;
+  int map_outer = 0, map_inner = 0, map_last_row = -1;
+  double *map_path = nullptr, *map_lp = nullptr;        // T x p, T
+  int *map_best = nullptr;
+  double *map_starts = nullptr, *map_modes = nullptr, *map_mlp = nullptr;
   // single-coordinate kernel operands (standardised genotype columns, labels)
   void *xs_ss = nullptr, *yv_ss = nullptr;
   // sparsity-path summaries (per scale, and the c-marginal mixture)
@@ -477,6 +485,60 @@ spa_status single_site_cycles(spa_smc *h, int t, int cycles, double lam) {
   return SPA_OK;
 }
 
+spa_status ensure_map_cols(spa_smc *h) {
+  if (h->map_xs) return SPA_OK;
+  spa_status st;
+  if ((st = dalloc(h, &h->map_xs, 8 * (size_t)h->p * h->n_pad)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_yv, 8 * (size_t)h->n_pad)) != SPA_OK) return st;
+  SPA_CK(h, launch_map_cols(h->dX, h->dy, h->n, h->p, h->n_pad, h->mu, h->s, h->map_xs, h->map_yv, h->stream));
+  return SPA_OK;
+}
+
+spa_status run_map_em(spa_smc *h, const void *beta0, bool in_f64, int M, double lam, int outer, int inner,
+                      double *mode, double *logpost) {
+  spa_status st;
+  if ((st = ensure_map_cols(h)) != SPA_OK) return st;
+  MapArgs a{};
+  a.xs = h->map_xs;
+  a.yv = h->map_yv;
+  a.beta0 = beta0;
+  a.mode = mode;
+  a.logpost = logpost;
+  a.prior = make_prior(h, lam);
+  a.M = M;
+  a.n = h->n;
+  a.n_pad = h->n_pad;
+  a.p = h->p;
+  a.outer = outer;
+  a.inner = inner;
+  tbeg(h, SPA_T_MAP);
+  SPA_CK(h, launch_map_em(in_f64, a, h->stream));
+  tend(h);
+  return SPA_OK;
+}
+
+// MAP path row `row` (Section 4.1): EM from the particle of highest posterior density at
+// this scale and from the previous row's MAP; the better mode is kept.
+spa_status record_map(spa_smc *h, int row) {
+  if (!h->map_on) return SPA_OK;
+  const double lam = h->lambda[row];
+  const Prior pr = make_prior(h, lam);
+  const int p = h->p;
+  const bool prev = h->map_last_row == row - 1 && row > 0;
+  tbeg(h, SPA_T_MAP);
+  SPA_CK(h, launch_best_particle(h->f64, h->beta, h->ll, h->N, p, pr, h->map_best, h->stream));
+  SPA_CK(h, launch_map_starts(h->f64, h->beta, h->map_best, p, prev ? h->map_path + (size_t)(row - 1) * p : nullptr,
+                              h->map_starts, h->stream));
+  tend(h);
+  const int ns = prev ? 2 : 1;
+  spa_status st = run_map_em(h, h->map_starts, true, ns, lam, h->map_outer, h->map_inner, h->map_modes, h->map_mlp);
+  if (st != SPA_OK) return st;
+  SPA_CK(h, launch_map_pick(h->map_modes, h->map_mlp, ns, p, h->map_path + (size_t)row * p, h->map_lp + row,
+                            h->stream));
+  h->map_last_row = row;
+  return SPA_OK;
+}
+
 // Summary scratch for M values of p coefficients.
 spa_status ensure_sq(spa_smc *h, size_t M, int p, bool f64) {
   spa_status st;
@@ -830,6 +892,7 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   if ((st = read_count(h, &cnt)) != SPA_OK) return st;
   if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_summaries(h, t_new - 1)) != SPA_OK) return st;
+  if ((st = record_map(h, t_new - 1)) != SPA_OK) return st;
   const double upd = static_cast<double>(h->N) * (h->move == SPA_MOVE_SINGLE ? h->p : 1);   // MH decisions per sweep
   const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (upd * h->sweeps) : NAN;
   if (h->sweeps > 0) adapt_step(h, acc_rate);
@@ -1043,6 +1106,49 @@ extern "C" spa_status spa_smc_get(const spa_smc *h, const void **beta_dev, const
   if (var_path_dev) *var_path_dev = h->var_path;
   if (logz_path_host) *logz_path_host = h->logz_path.data();
   if (t_out) *t_out = h->t;
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_map_em(spa_smc *h, const void *beta0_dev, int32_t M, int32_t beta_is_fp64,
+                                 double lambda, int32_t outer, int32_t inner, double *mode_dev,
+                                 double *logpost_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!beta0_dev || !mode_dev || !logpost_dev) return set_err(h, SPA_ERR_ARG, "NULL pointer");
+  if (M < 1) return set_err(h, SPA_ERR_SHAPE, "M must be >= 1");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return set_err(h, SPA_ERR_ARG, "lambda must be > 0");
+  if (outer < 0 || inner < 0) return set_err(h, SPA_ERR_ARG, "iteration counts must be >= 0");
+  if (h->n > map_max_n() || h->p > kMapMaxP) return set_err(h, SPA_ERR_SHAPE, "n > 10240 or p > 512");
+  return run_map_em(h, beta0_dev, beta_is_fp64 != 0, M, lambda, outer, inner, mode_dev, logpost_dev);
+}
+
+extern "C" spa_status spa_smc_set_map(spa_smc *h, int32_t outer, int32_t inner) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (h->t < 1) return set_err(h, SPA_ERR_STATE, "handle not initialised");
+  if (h->map_on) return set_err(h, SPA_ERR_STATE, "MAP path already configured");
+  if (outer < 0 || inner < 0) return set_err(h, SPA_ERR_ARG, "iteration counts must be >= 0");
+  if (h->n > map_max_n() || h->p > kMapMaxP) return set_err(h, SPA_ERR_SHAPE, "n > 10240 or p > 512");
+  spa_status st;
+  const size_t T = h->T, p = h->p;
+  if ((st = dalloc(h, &h->map_path, 8 * T * p)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_lp, 8 * T)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_best, 16)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_starts, 8 * 2 * p)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_modes, 8 * 2 * p)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_mlp, 16)) != SPA_OK) return st;
+  h->map_on = true;
+  h->map_outer = outer;
+  h->map_inner = inner;
+  if ((st = record_map(h, h->t - 1)) != SPA_OK) return st;
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  return SPA_OK;
+}
+
+extern "C" spa_status spa_smc_get_map(const spa_smc *h, const double **map_path_dev, const double **logpost_path_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!h->map_on) return SPA_ERR_STATE;
+  if (map_path_dev) *map_path_dev = h->map_path;
+  if (logpost_path_dev) *logpost_path_dev = h->map_lp;
   return SPA_OK;
 }
 

@@ -121,6 +121,10 @@ def test_null_handle_calls(lib):
     assert lib.spa_smc_set_summaries(None, None, 0, None, 0, 0) == binding.SPA_ERR_ARG
     assert lib.spa_smc_get_summaries(None, None, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_marginal_summaries(None, None, None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_map_em(None, None, 1, 0, 1.0, 1, 1, None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_set_map(None, 1, 1) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_get_map(None, None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_get_loglik(None, None) == binding.SPA_ERR_ARG
     lib.spa_smc_destroy(None)
 
 
