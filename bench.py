@@ -112,6 +112,35 @@ def single_site_leg(steps: int = 10):
                          "frac": round(rate_k * SINGLE_SITE_SLOTS / VALU_LANE_SLOTS_PER_S, 4)}}
 
 
+def analysis_legs(torch, s, cfg):
+    """Timings of the sparsity-path analysis on the bench workload's live particles:
+    per-scale summaries (3 quantile levels, 2 tolerances) and one MAP-path scale (EM from
+    two start points, 50 E steps x 5 coordinate sweeps)."""
+    beta, logw = s.particles()
+    w = torch.exp(logw - logw.max())
+    s.weighted_summaries(beta, w)                 # warm-up (allocates its scratch)
+    torch.cuda.synchronize()
+    K = 5
+    t0 = time.perf_counter()
+    for _ in range(K):
+        s.weighted_summaries(beta, w)
+    torch.cuda.synchronize()
+    t_sum = (time.perf_counter() - t0) / K
+    starts = beta[:2].double()
+    s.map_em(starts, float(cfg.grid()[min(10, cfg.T - 1)]), 1, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.map_em(starts, float(cfg.grid()[min(10, cfg.T - 1)]), 50, 5)
+    torch.cuda.synchronize()
+    t_map = time.perf_counter() - t0
+    vbytes = cfg.N * cfg.p * beta.element_size()
+    return {"summaries": {"ms": round(t_sum * 1e3, 3), "values_GBps": round(vbytes / t_sum / 1e9, 1),
+                          "what": f"quantiles (0.05, 0.5, 0.95) and V(0.05), V(0.1) of {cfg.p} coefficients "
+                                  f"over N={cfg.N} weighted particles"},
+            "map_em": {"ms": round(t_map * 1e3, 3),
+                       "what": f"EM from 2 start points, 50 E steps x 5 coordinate sweeps, n={cfg.n} p={cfg.p}"}}
+
+
 def gemm_flops(cfg) -> float:
     """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
     f = 2.0 * cfg.N * cfg.n * cfg.p
@@ -282,6 +311,7 @@ def main():
         "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in tim.items()},
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
+    out["analysis"] = analysis_legs(torch, s, cfg)
     s.close()
     if not args.no_single:
         out["single_site"] = single_site_leg()
