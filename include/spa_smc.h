@@ -290,9 +290,11 @@ spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uin
  * launch; it is off by default.  Errors: SPA_ERR_ARG (null pointers).
  */
 enum {
-  SPA_T_PROPOSE = 0,    /* proposal + scaled-coefficient operand                      */
+  SPA_T_PROPOSE = 0,    /* proposal + scaled-coefficient operand (first sweep of a   */
+                        /* step; burn-in sweeps; single-coordinate cycles)             */
   SPA_T_LOGLIK = 1,     /* MFMA log-likelihood contraction (+ adjoint for MALA)        */
-  SPA_T_ACCEPT = 2,     /* Metropolis-Hastings decisions                               */
+  SPA_T_ACCEPT = 2,     /* Metropolis-Hastings decisions; within a step, every sweep */
+                        /* but the last also draws the next sweep's proposal here      */
   SPA_T_REWEIGHT = 3,   /* prior-ratio incremental weights                             */
   SPA_T_LSE = 4,        /* logsumexp / ESS / systematic resampling                     */
   SPA_T_GATHER = 5,     /* particle gather after resampling                            */
@@ -304,6 +306,16 @@ enum {
 };
 spa_status spa_smc_set_timing(spa_smc *h, int32_t enable);
 spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches);
+
+/*
+ * Timing of chosen classes only: bit c of class_mask brackets the launches of class c
+ * (spa_smc_set_timing(h, 1) is the mask of all classes, 0 turns timing off).  Like
+ * spa_smc_set_timing it synchronises the stream and resets the counters.  Each bracketed
+ * launch costs a pair of event records on the stream, so timing one class (say the
+ * contraction) perturbs the measured run far less than timing all of them.
+ * Errors: SPA_ERR_ARG (null handle, bits at or above SPA_TIMING_CLASSES).
+ */
+spa_status spa_smc_set_timing_classes(spa_smc *h, uint32_t class_mask);
 
 /* Release every resource of the handle (NULL is a no-op). */
 void spa_smc_destroy(spa_smc *h);

@@ -31,7 +31,8 @@ EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "sp
            "spa_smc_marginal_summaries", "spa_map_em", "spa_smc_set_map", "spa_smc_get_map",
            "spa_smc_get", "spa_smc_get_loglik", "spa_smc_get_stats", "spa_smc_set_state",
            "spa_philox4x32_10",
-           "spa_smc_set_timing", "spa_smc_get_timing", "spa_smc_destroy", "spa_smc_last_error"]
+           "spa_smc_set_timing", "spa_smc_set_timing_classes", "spa_smc_get_timing", "spa_smc_destroy",
+           "spa_smc_last_error"]
 TIMING_CLASSES = ["propose", "loglik", "accept", "reweight", "lse_resample", "gather", "moments",
                   "finalize", "summary", "map"]
 
@@ -98,6 +99,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spa_smc_set_state.argtypes = [vp, vp, vp, i32, dbl]
     lib.spa_philox4x32_10.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
     lib.spa_smc_set_timing.argtypes = [vp, i32]
+    lib.spa_smc_set_timing_classes.argtypes = [vp, ctypes.c_uint32]
     lib.spa_smc_get_timing.argtypes = [vp, vp, vp]
     lib.spa_smc_destroy.argtypes = [vp]
     lib.spa_smc_destroy.restype = None
@@ -389,8 +391,18 @@ class SpaSMC:
         self.stream.synchronize()
         return m[:t].cpu().numpy(), v[:t].cpu().numpy()
 
-    def set_timing(self, enable: bool = True):
-        self._check(self.lib.spa_smc_set_timing(self.h, int(bool(enable))))
+    def set_timing(self, enable: bool = True, classes=None):
+        """Bracket launches with HIP events: every class, or only the named ones
+        (names from TIMING_CLASSES); set_timing(False) turns timing off."""
+        if classes is None:
+            self._check(self.lib.spa_smc_set_timing(self.h, int(bool(enable))))
+            return
+        mask = 0
+        for c in classes:
+            if c not in TIMING_CLASSES:
+                raise ValueError(f"unknown timing class {c!r}")
+            mask |= 1 << TIMING_CLASSES.index(c)
+        self._check(self.lib.spa_smc_set_timing_classes(self.h, mask if enable else 0))
 
     def timing(self) -> dict:
         """{class: (total ms, launches)} accumulated since set_timing(True)."""

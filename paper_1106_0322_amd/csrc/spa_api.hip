@@ -113,6 +113,8 @@ struct spa_smc {
   std::vector<void *> allocs;
   // optional per-kernel-class timing with HIP events on the handle's stream
   bool timing = false;
+  uint32_t tmask = 0;              // bit c: launches of class c are bracketed
+  bool topen = false;              // a tbeg of a timed class awaits its tend
   std::vector<hipEvent_t> ev;      // pool, used in (start, stop) pairs
   std::vector<int> ev_cat;         // category of each recorded pair
   double t_ms[SPA_TIMING_CLASSES] = {0};
@@ -208,7 +210,8 @@ Prior make_prior(const spa_smc *h, double lam) {
 
 // ---- timing: tbeg/tend bracket one launch; flush after a synchronisation point
 void tbeg(spa_smc *h, int cat) {
-  if (!h->timing) return;
+  h->topen = false;
+  if (!h->timing || !((h->tmask >> cat) & 1u)) return;
   const size_t k = 2 * h->ev_cat.size();
   while (h->ev.size() < k + 2) {
     hipEvent_t e;
@@ -220,9 +223,11 @@ void tbeg(spa_smc *h, int cat) {
   }
   h->ev_cat.push_back(cat);
   (void)hipEventRecord(h->ev[k], h->stream);
+  h->topen = true;
 }
 void tend(spa_smc *h) {
-  if (!h->timing || h->ev_cat.empty()) return;
+  if (!h->topen) return;
+  h->topen = false;
   (void)hipEventRecord(h->ev[2 * h->ev_cat.size() - 1], h->stream);
 }
 void tflush(spa_smc *h) {   // the stream must be synchronised
@@ -359,7 +364,10 @@ spa_status eval_state(spa_smc *h, const void *beta, double *ll, void *g) {
 }
 
 // One sweep targeting pi(. | lam): propose -> contraction (+ adjoint) -> MH decision.
-spa_status sweep(spa_smc *h, int t, int s, double lam) {
+// have_prop: the previous sweep's decision kernel already drew this sweep's proposal;
+// make_next: this sweep's decision kernel draws the proposal of sweep s + 1 (the caller
+// keeps the step size, the preconditioner and lam fixed until that sweep).
+spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, bool make_next = false) {
   const bool mala = h->move == SPA_MOVE_MALA;
   const Prior pr = make_prior(h, lam);
   ProposeArgs pa{};
@@ -389,9 +397,11 @@ spa_status sweep(spa_smc *h, int t, int s, double lam) {
   pa.k1 = h->k1;
   pa.sweep = static_cast<uint32_t>(s);
   pa.t = t;
-  tbeg(h, SPA_T_PROPOSE);
-  launch_propose(h->prec, mala, pa, h->stream);
-  tend(h);
+  if (!have_prop) {
+    tbeg(h, SPA_T_PROPOSE);
+    launch_propose(h->prec, mala, pa, h->stream);
+    tend(h);
+  }
   GemmArgs ga;
   spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr, false, &ga);
   if (st != SPA_OK) return st;
@@ -426,8 +436,10 @@ spa_status sweep(spa_smc *h, int t, int s, double lam) {
   aa.k1 = h->k1;
   aa.sweep = static_cast<uint32_t>(s);
   aa.t = t;
+  ProposeArgs na = pa;
+  na.sweep = static_cast<uint32_t>(s + 1);
   tbeg(h, SPA_T_ACCEPT);
-  launch_accept(h->f64, mala, aa, h->stream);
+  launch_accept(h->prec, mala, aa, make_next ? &na : nullptr, h->stream);
   tend(h);
   SPA_CK(h, hipGetLastError());
   return SPA_OK;
@@ -886,7 +898,7 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
     if (h->sweeps > 0 && (st = single_site_cycles(h, t_new, h->sweeps, lam_new)) != SPA_OK) return st;
   } else {
     for (int s = 0; s < h->sweeps; ++s)
-      if ((st = sweep(h, t_new, s, lam_new)) != SPA_OK) return st;
+      if ((st = sweep(h, t_new, s, lam_new, s > 0, s + 1 < h->sweeps)) != SPA_OK) return st;
   }
   long long cnt = 0;
   if ((st = read_count(h, &cnt)) != SPA_OK) return st;
@@ -1202,10 +1214,17 @@ extern "C" spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int
 }
 
 extern "C" spa_status spa_smc_set_timing(spa_smc *h, int32_t enable) {
+  return spa_smc_set_timing_classes(h, enable ? (1u << SPA_TIMING_CLASSES) - 1u : 0u);
+}
+
+extern "C" spa_status spa_smc_set_timing_classes(spa_smc *h, uint32_t class_mask) {
   if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (class_mask >> SPA_TIMING_CLASSES) return set_err(h, SPA_ERR_ARG, "timing class mask has unknown bits");
   SPA_CK(h, hipStreamSynchronize(h->stream));
   tflush(h);
-  h->timing = enable != 0;
+  h->tmask = class_mask;
+  h->timing = class_mask != 0;
+  h->topen = false;
   for (int c = 0; c < SPA_TIMING_CLASSES; ++c) {
     h->t_ms[c] = 0.0;
     h->t_cnt[c] = 0;

@@ -237,23 +237,24 @@ __device__ __forceinline__ void store4(T *dst, bool vec, int j0, int lim, const 
   }
 }
 
-// One proposal sweep: beta' from beta (random walk or MALA), the B operand of beta',
-// and per-particle log prior terms.  Lane l handles markers 4l..4l+3 (one Philox block).
-// The prior and proposal arithmetic runs in the particle precision PT; the log prior of
-// a block of four coefficients is one log of the product of their factors.
+// Particle rows in registers: lane l holds markers 4l..4l+3 and 256+4l..256+4l+3 (one
+// Philox block of four normals each), which covers p <= 511.
+constexpr int kRowBlocks = 2;
+
+// The proposal of one particle row (random walk or MALA) from its current coefficients
+// and likelihood gradient (in registers, zero outside the row), the B operand of the
+// proposal and the per-particle log prior terms.  The prior and proposal arithmetic runs
+// in the particle precision PT; the log prior of a block of four coefficients is one log
+// of the product of their factors.  `live` is false for padded particles (i >= M), which
+// get a zero operand row.
 template <Prec P, typename PT, bool MALA>
-__global__ void propose_kernel(ProposeArgs a) {
+__device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, const int lane, const bool live,
+                                            const PT (&cur)[kRowBlocks][4], const PT (&gv)[kRowBlocks][4]) {
   using BT = typename BPack<P>::BT;
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= a.M_pad) return;
   const int p = a.p, PP = a.PP;
-  const PT *beta = reinterpret_cast<const PT *>(a.beta) + (size_t)i * p;
-  const PT *gl = reinterpret_cast<const PT *>(a.gl) + (size_t)i * p;
   PT *prop = reinterpret_cast<PT *>(a.prop) + (size_t)i * p;
   BT *Bhi = reinterpret_cast<BT *>(a.Bhi);
   BT *Blo = reinterpret_cast<BT *>(a.Blo);
-  const bool live = i < a.M;
   const bool vrow = (p & 3) == 0;   // particle rows keep 4-marker blocks aligned
   const Prior pr = a.prior;
   const PT inv_ac = pr.inf ? PT(0) : static_cast<PT>(1.0 / (pr.a * pr.lam));
@@ -261,8 +262,11 @@ __global__ void propose_kernel(ProposeArgs a) {
   const PT inv_c = static_cast<PT>(1.0 / pr.lam);
   const PT step = static_cast<PT>(a.step), sqrt_step = static_cast<PT>(a.sqrt_step);
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
-  for (int b0 = lane * 4; b0 < PP; b0 += 256) {
-    PT z[4] = {0, 0, 0, 0}, cur[4] = {0, 0, 0, 0}, gv[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int kb = 0; kb < kRowBlocks; ++kb) {
+    const int b0 = lane * 4 + 256 * kb;
+    if (b0 >= PP) continue;
+    PT z[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
     double sgd[4], invs[4], mu4[4], yt4[4], s4[4];
     load4(a.sigma, true, b0, p, sgd);
     load4(a.cc.inv_s, true, b0, PP, invs);
@@ -270,34 +274,32 @@ __global__ void propose_kernel(ProposeArgs a) {
     load4(a.cc.ytil, true, b0, PP, yt4);
     load4(a.cc.s, true, b0, PP, s4);
     const bool act = live && b0 < p;
-    if (act) {
+    if (act)
       block_normals(philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(b0 >> 2), a.sweep,
                                              word3(a.t, kTagNormal)),
                                   a.k0, a.k1),
                     z);
-      load4(beta, vrow, b0, p, cur);
-      if constexpr (MALA) load4(gl, vrow, b0, p, gv);
-    }
     PT fc = PT(1), fp = PT(1), lc = PT(0), lpn = PT(0), q = PT(0);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j = b0 + k;
       if (act && j < p) {
         const PT sg = static_cast<PT>(sgd[k]);
+        const PT c = cur[kb][k];
         if constexpr (MALA) {
-          const PT g = gv[k] + gt_grad_t<PT>(cur[k], a1, ac, pr.inf, inv_c);
-          const PT meanf = cur[k] + PT(0.5) * step * sg * sg * g;
+          const PT g = gv[kb][k] + gt_grad_t<PT>(c, a1, ac, pr.inf, inv_c);
+          const PT meanf = c + PT(0.5) * step * sg * sg * g;
           nv[k] = meanf + sqrt_step * sg * z[k];
           const PT d = nv[k] - meanf;
           q += d * d / (PT(2) * step * sg * sg);
         } else {
-          nv[k] = cur[k] + step * sg * z[k];
+          nv[k] = c + step * sg * z[k];
         }
         if (pr.inf) {
-          lc += fabs(cur[k]);
+          lc += fabs(c);
           lpn += fabs(nv[k]);
         } else {
-          fc *= gt_factor<PT>(cur[k], inv_ac);
+          fc *= gt_factor<PT>(c, inv_ac);
           fp *= gt_factor<PT>(nv[k], inv_ac);
         }
       }
@@ -343,50 +345,97 @@ __global__ void propose_kernel(ProposeArgs a) {
   }
 }
 
+// Load a particle row into the register layout above (zero outside the row).
+template <typename PT>
+__device__ __forceinline__ void load_row(const PT *row, const int lane, const int p, PT (&v)[kRowBlocks][4]) {
+  const bool vrow = (p & 3) == 0;
+#pragma unroll
+  for (int kb = 0; kb < kRowBlocks; ++kb) {
+    const int b0 = lane * 4 + 256 * kb;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[kb][k] = PT(0);
+    if (b0 < p) load4(row, vrow, b0, p, v[kb]);
+  }
+}
+
+template <typename PT>
+__device__ __forceinline__ void store_row(PT *row, const int lane, const int p, const PT (&v)[kRowBlocks][4]) {
+  const bool vrow = (p & 3) == 0;
+#pragma unroll
+  for (int kb = 0; kb < kRowBlocks; ++kb) {
+    const int b0 = lane * 4 + 256 * kb;
+    if (b0 < p) store4(row, vrow, b0, p, v[kb]);
+  }
+}
+
+// One proposal sweep over all (padded) particle rows; one wave per particle.
+template <Prec P, typename PT, bool MALA>
+__global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (i >= a.M_pad) return;
+  const bool live = i < a.M;
+  PT cur[kRowBlocks][4], gv[kRowBlocks][4];
+  const int p = live ? a.p : 0;   // padded particles: all-zero rows
+  load_row(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
+  if constexpr (MALA) load_row(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
+  else load_row(static_cast<const PT *>(nullptr), lane, 0, gv);
+  propose_row<P, PT, MALA>(a, i, lane, live, cur, gv);
+}
+
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
 // PARTS: the proposal's log-likelihood and likelihood gradient are combined from the split
-// contraction's partial sums (kept in registers: lane l holds markers l, l+64, ...).
-constexpr int kAccMaxPerLane = 8;   // p <= 511
-template <typename PT, bool MALA, bool PARTS>
-__global__ void accept_kernel(AcceptArgs a) {
+// contraction's partial sums.  NEXT: the wave then draws the next sweep's proposal from
+// the row it has just decided (the state after this decision, still in registers), so the
+// next sweep needs no separate proposal launch; valid while the proposal scale, the step
+// size and the prior stay fixed between the two sweeps.
+template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT>
+__global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs na) {
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= a.M) return;
-  PT *beta = reinterpret_cast<PT *>(a.beta);
-  PT *gl = reinterpret_cast<PT *>(a.gl);
-  const PT *prop = reinterpret_cast<const PT *>(a.prop);
-  const PT *glp = reinterpret_cast<const PT *>(a.gl_prop);
   const int p = a.p;
+  PT *beta = reinterpret_cast<PT *>(a.beta) + (size_t)i * p;
+  PT *gl = reinterpret_cast<PT *>(a.gl) + (size_t)i * p;
   const Prior pr = a.prior;
+  PT nv[kRowBlocks][4], cur[kRowBlocks][4], gnew[kRowBlocks][4];
+  load_row(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
+  load_row(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
   double llp;
-  PT gnew[MALA ? kAccMaxPerLane : 1];
   if constexpr (PARTS) {
     double spl = 0.0;
     for (int s = 0; s < a.S; ++s) spl += a.spl_part[s * a.Mp + i];
     llp = a.yb[i] - spl;
     if constexpr (MALA) {
       const PT *gp = reinterpret_cast<const PT *>(a.g_part);
+      const int PP = a.PP;
       double rho = 0.0;
-      for (int s = 0; s < a.S; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * a.PP + a.PP - 1]);
+      for (int s = 0; s < a.S; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * PP + PP - 1]);
 #pragma unroll
-      for (int k = 0; k < kAccMaxPerLane; ++k) {
-        const int j = lane + 64 * k;
-        if (j < p) {
-          double acc = 0.0;
-          for (int s = 0; s < a.S; ++s) acc += static_cast<double>(gp[(s * a.Mp + i) * a.PP + j]);
-          gnew[k] = static_cast<PT>(a.ytil[j] - (acc - a.mu[j] * rho) * a.inv_s[j]);
+      for (int kb = 0; kb < kRowBlocks; ++kb) {
+        const int b0 = lane * 4 + 256 * kb;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) gnew[kb][k] = PT(0);
+        if (b0 >= p) continue;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < a.S; ++s) {   // rows are PP long, PP a multiple of 32: aligned blocks
+          PT t4[4];
+          load4(gp + (s * a.Mp + i) * PP, true, b0, PP, t4);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) acc[k] += static_cast<double>(t4[k]);
         }
+        double yt4[4], mu4[4], is4[4];
+        load4(a.ytil, true, b0, PP, yt4);
+        load4(a.mu, true, b0, PP, mu4);
+        load4(a.inv_s, true, b0, PP, is4);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (b0 + k < p) gnew[kb][k] = static_cast<PT>(yt4[k] - (acc[k] - mu4[k] * rho) * is4[k]);
       }
     }
   } else {
     llp = a.ll_prop[i];
-    if constexpr (MALA) {
-#pragma unroll
-      for (int k = 0; k < kAccMaxPerLane; ++k) {
-        const int j = lane + 64 * k;
-        if (j < p) gnew[k] = glp[(size_t)i * p + j];
-      }
-    }
+    if constexpr (MALA) load_row(reinterpret_cast<const PT *>(a.gl_prop) + (size_t)i * p, lane, p, gnew);
   }
   double lqr = 0.0;
   if constexpr (MALA) {
@@ -394,16 +443,20 @@ __global__ void accept_kernel(AcceptArgs a) {
     const PT inv_c = static_cast<PT>(1.0 / pr.lam), step = static_cast<PT>(a.step);
     PT q = PT(0);
 #pragma unroll
-    for (int k = 0; k < kAccMaxPerLane; ++k) {
-      const int j = lane + 64 * k;
-      if (j < p) {
-        const size_t off = (size_t)i * p + j;
-        const PT nv = prop[off];
-        const PT sg = static_cast<PT>(a.sigma[j]);
-        const PT g = gnew[k] + gt_grad_t<PT>(nv, a1, ac, pr.inf, inv_c);
-        const PT meanr = nv + PT(0.5) * step * sg * sg * g;
-        const PT d = beta[off] - meanr;
-        q += d * d / (PT(2) * step * sg * sg);
+    for (int kb = 0; kb < kRowBlocks; ++kb) {
+      const int b0 = lane * 4 + 256 * kb;
+      if (b0 >= p) continue;
+      double sgd[4];
+      load4(a.sigma, true, b0, p, sgd);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (b0 + k < p) {
+          const PT sg = static_cast<PT>(sgd[k]);
+          const PT g = gnew[kb][k] + gt_grad_t<PT>(nv[kb][k], a1, ac, pr.inf, inv_c);
+          const PT meanr = nv[kb][k] + PT(0.5) * step * sg * sg * g;
+          const PT d = cur[kb][k] - meanr;
+          q += d * d / (PT(2) * step * sg * sg);
+        }
       }
     }
     lqr = -wave_sum(static_cast<double>(q));
@@ -412,20 +465,38 @@ __global__ void accept_kernel(AcceptArgs a) {
   const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
                                 a.k0, a.k1);
   const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
-  const bool acc = log(u) < log_alpha;   // false for NaN
+  const bool acc = log(u) < log_alpha;   // false for NaN; the same in every lane
   if (acc) {
-#pragma unroll
-    for (int k = 0; k < kAccMaxPerLane; ++k) {
-      const int j = lane + 64 * k;
-      if (j < p) {
-        const size_t off = (size_t)i * p + j;
-        beta[off] = prop[off];
-        if constexpr (MALA) gl[off] = gnew[k];
-      }
-    }
+    store_row(beta, lane, p, nv);
+    if constexpr (MALA) store_row(gl, lane, p, gnew);
     if (lane == 0) a.ll[i] = llp;
   }
   if (lane == 0) a.acc_cnt[i] += acc ? 1 : 0;
+  if constexpr (NEXT) {
+    PT gv[kRowBlocks][4];
+    if constexpr (MALA) {
+      if (acc) {
+#pragma unroll
+        for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            cur[kb][k] = nv[kb][k];
+            gv[kb][k] = gnew[kb][k];
+          }
+      } else {
+        load_row(const_cast<const PT *>(gl), lane, p, gv);
+      }
+    } else {
+#pragma unroll
+      for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (acc) cur[kb][k] = nv[kb][k];
+          gv[kb][k] = PT(0);
+        }
+    }
+    propose_row<P, PT, MALA>(na, i, lane, true, cur, gv);
+  }
 }
 
 // ================================================================ weights
@@ -808,22 +879,31 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) 
 #undef SPA_PROP
 }
 
-template <typename PT>
-static void launch_accept_t(bool mala, const AcceptArgs &a, hipStream_t st) {
+template <Prec P, typename PT, bool MALA, bool NEXT>
+static void launch_accept_t(bool parts, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
   const int grid = grid_rows(a.M, 4);
-  const bool parts = a.spl_part != nullptr;
-  if (mala) {
-    if (parts) hipLaunchKernelGGL((accept_kernel<PT, true, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((accept_kernel<PT, true, false>), dim3(grid), dim3(256), 0, st, a);
+  if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT>), dim3(grid), dim3(256), 0, st, a, na);
+  else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT>), dim3(grid), dim3(256), 0, st, a, na);
+}
+
+template <Prec P, typename PT>
+static void launch_accept_p(bool mala, bool parts, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
+  const ProposeArgs none{};
+  if (next) {
+    if (mala) launch_accept_t<P, PT, true, true>(parts, a, *next, st);
+    else launch_accept_t<P, PT, false, true>(parts, a, *next, st);
   } else {
-    if (parts) hipLaunchKernelGGL((accept_kernel<PT, false, true>), dim3(grid), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((accept_kernel<PT, false, false>), dim3(grid), dim3(256), 0, st, a);
+    if (mala) launch_accept_t<P, PT, true, false>(parts, a, none, st);
+    else launch_accept_t<P, PT, false, false>(parts, a, none, st);
   }
 }
 
-void launch_accept(bool f64, bool mala, const AcceptArgs &a, hipStream_t st) {
-  if (f64) launch_accept_t<double>(mala, a, st);
-  else launch_accept_t<float>(mala, a, st);
+void launch_accept(Prec prec, bool mala, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
+  const bool parts = a.spl_part != nullptr;
+  if (prec == Prec::F64) launch_accept_p<Prec::F64, double>(mala, parts, a, next, st);
+  else if (prec == Prec::F32) launch_accept_p<Prec::F32, float>(mala, parts, a, next, st);
+  else if (next) launch_accept_p<Prec::BF16X2, float>(mala, parts, a, next, st);
+  else launch_accept_p<Prec::F32, float>(mala, parts, a, next, st);   // no operand written: one instance
 }
 
 void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,

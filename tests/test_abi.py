@@ -125,6 +125,8 @@ def test_null_handle_calls(lib):
     assert lib.spa_smc_set_map(None, 1, 1) == binding.SPA_ERR_ARG
     assert lib.spa_smc_get_map(None, None, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_get_loglik(None, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_set_timing(None, 1) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_set_timing_classes(None, 2) == binding.SPA_ERR_ARG
     lib.spa_smc_destroy(None)
 
 

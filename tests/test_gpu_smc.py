@@ -165,6 +165,29 @@ def test_determinism_same_seed():
         assert np.array_equal(a, b)
 
 
+def test_timing_classes_bracket_only_the_named_kernels():
+    cfg, X, y, Xs = dataset("cfg1")
+    cfg = cfg.replace(N=1024, T=6, sweeps=2, init_sweeps=2, prec="bf16x2", move="mala")
+    g = _gpu(cfg, X, y)
+    g.set_timing(True, classes=["loglik"])
+    g.step()
+    t = g.timing()
+    assert t["loglik"][1] == cfg.sweeps and t["loglik"][0] > 0.0
+    assert all(v == (0.0, 0) for k, v in t.items() if k != "loglik")
+    g.set_timing(True)
+    g.step()
+    t = g.timing()
+    # the first sweep's proposal has a launch of its own; the decision kernel of every
+    # other sweep draws the next sweep's proposal
+    assert t["loglik"][1] == cfg.sweeps and t["propose"][1] == 1 and t["accept"][1] == cfg.sweeps
+    g.set_timing(False)
+    g.step()
+    assert all(v == (0.0, 0) for v in g.timing().values())
+    with pytest.raises(ValueError):
+        g.set_timing(True, classes=["no such class"])
+    g.close()
+
+
 @pytest.mark.parametrize("name,init", [("cfg3", 4), ("cfg4", 2), ("cfg3_rwm32", 4)])
 def test_full_size_sampled_parity(name, init):
     """The live particle system at the full workload size and launch configuration:
