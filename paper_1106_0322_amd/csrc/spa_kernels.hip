@@ -237,9 +237,19 @@ __device__ __forceinline__ void store4(T *dst, bool vec, int j0, int lim, const 
   }
 }
 
-// Particle rows in registers: lane l holds markers 4l..4l+3 and 256+4l..256+4l+3 (one
-// Philox block of four normals each), which covers p <= 511.
+// Particle rows in registers: LP lanes per particle (64, or 32 for rows of at most 256
+// markers, two particles per wave); sub-lane l holds markers 4l..4l+3 and
+// 4LP+4l..4LP+4l+3 (one Philox block of four normals each), which covers p <= 8 LP - 1.
 constexpr int kRowBlocks = 2;
+
+// Sum over the LP lanes of a particle (fixed xor-butterfly order; the same value in every
+// lane of the group).
+template <int LP>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = LP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
 
 // The proposal of one particle row (random walk or MALA) from its current coefficients
 // and likelihood gradient (in registers, zero outside the row), the B operand of the
@@ -247,7 +257,7 @@ constexpr int kRowBlocks = 2;
 // in the particle precision PT; the log prior of a block of four coefficients is one log
 // of the product of their factors.  `live` is false for padded particles (i >= M), which
 // get a zero operand row.
-template <Prec P, typename PT, bool MALA>
+template <Prec P, typename PT, bool MALA, int LP>
 __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, const int lane, const bool live,
                                             const PT (&cur)[kRowBlocks][4], const PT (&gv)[kRowBlocks][4]) {
   using BT = typename BPack<P>::BT;
@@ -264,7 +274,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
 #pragma unroll
   for (int kb = 0; kb < kRowBlocks; ++kb) {
-    const int b0 = lane * 4 + 256 * kb;
+    const int b0 = lane * 4 + 4 * LP * kb;
     if (b0 >= PP) continue;
     PT z[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
     double sgd[4], invs[4], mu4[4], yt4[4], s4[4];
@@ -326,11 +336,11 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
     }
     lqf -= static_cast<double>(q);
   }
-  m = wave_sum(m);
-  ybv = wave_sum(ybv);
-  lpc = wave_sum(lpc);
-  lpp = wave_sum(lpp);
-  if constexpr (MALA) lqf = wave_sum(lqf);
+  m = group_sum<LP>(m);
+  ybv = group_sum<LP>(ybv);
+  lpc = group_sum<LP>(lpc);
+  lpp = group_sum<LP>(lpp);
+  if constexpr (MALA) lqf = group_sum<LP>(lqf);
   if (lane == 0) {
     a.moff[i] = m;
     a.yb[i] = ybv / BPack<P>::scale;
@@ -346,41 +356,41 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
 }
 
 // Load a particle row into the register layout above (zero outside the row).
-template <typename PT>
+template <int LP, typename PT>
 __device__ __forceinline__ void load_row(const PT *row, const int lane, const int p, PT (&v)[kRowBlocks][4]) {
   const bool vrow = (p & 3) == 0;
 #pragma unroll
   for (int kb = 0; kb < kRowBlocks; ++kb) {
-    const int b0 = lane * 4 + 256 * kb;
+    const int b0 = lane * 4 + 4 * LP * kb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[kb][k] = PT(0);
     if (b0 < p) load4(row, vrow, b0, p, v[kb]);
   }
 }
 
-template <typename PT>
+template <int LP, typename PT>
 __device__ __forceinline__ void store_row(PT *row, const int lane, const int p, const PT (&v)[kRowBlocks][4]) {
   const bool vrow = (p & 3) == 0;
 #pragma unroll
   for (int kb = 0; kb < kRowBlocks; ++kb) {
-    const int b0 = lane * 4 + 256 * kb;
+    const int b0 = lane * 4 + 4 * LP * kb;
     if (b0 < p) store4(row, vrow, b0, p, v[kb]);
   }
 }
 
-// One proposal sweep over all (padded) particle rows; one wave per particle.
-template <Prec P, typename PT, bool MALA>
+// One proposal sweep over all (padded) particle rows; LP lanes per particle.
+template <Prec P, typename PT, bool MALA, int LP>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (LP - 1);
+  const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
   if (i >= a.M_pad) return;
   const bool live = i < a.M;
   PT cur[kRowBlocks][4], gv[kRowBlocks][4];
   const int p = live ? a.p : 0;   // padded particles: all-zero rows
-  load_row(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
-  if constexpr (MALA) load_row(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
-  else load_row(static_cast<const PT *>(nullptr), lane, 0, gv);
-  propose_row<P, PT, MALA>(a, i, lane, live, cur, gv);
+  load_row<LP>(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
+  if constexpr (MALA) load_row<LP>(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
+  else load_row<LP>(static_cast<const PT *>(nullptr), lane, 0, gv);
+  propose_row<P, PT, MALA, LP>(a, i, lane, live, cur, gv);
 }
 
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
@@ -389,18 +399,18 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
 // the row it has just decided (the state after this decision, still in registers), so the
 // next sweep needs no separate proposal launch; valid while the proposal scale, the step
 // size and the prior stay fixed between the two sweeps.
-template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT>
+template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT, int LP>
 __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs na) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (LP - 1);
+  const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
   if (i >= a.M) return;
   const int p = a.p;
   PT *beta = reinterpret_cast<PT *>(a.beta) + (size_t)i * p;
   PT *gl = reinterpret_cast<PT *>(a.gl) + (size_t)i * p;
   const Prior pr = a.prior;
   PT nv[kRowBlocks][4], cur[kRowBlocks][4], gnew[kRowBlocks][4];
-  load_row(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
-  load_row(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
+  load_row<LP>(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
+  load_row<LP>(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
   double llp;
   if constexpr (PARTS) {
     double spl = 0.0;
@@ -413,7 +423,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
       for (int s = 0; s < a.S; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * PP + PP - 1]);
 #pragma unroll
       for (int kb = 0; kb < kRowBlocks; ++kb) {
-        const int b0 = lane * 4 + 256 * kb;
+        const int b0 = lane * 4 + 4 * LP * kb;
 #pragma unroll
         for (int k = 0; k < 4; ++k) gnew[kb][k] = PT(0);
         if (b0 >= p) continue;
@@ -435,7 +445,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
     }
   } else {
     llp = a.ll_prop[i];
-    if constexpr (MALA) load_row(reinterpret_cast<const PT *>(a.gl_prop) + (size_t)i * p, lane, p, gnew);
+    if constexpr (MALA) load_row<LP>(reinterpret_cast<const PT *>(a.gl_prop) + (size_t)i * p, lane, p, gnew);
   }
   double lqr = 0.0;
   if constexpr (MALA) {
@@ -444,7 +454,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
     PT q = PT(0);
 #pragma unroll
     for (int kb = 0; kb < kRowBlocks; ++kb) {
-      const int b0 = lane * 4 + 256 * kb;
+      const int b0 = lane * 4 + 4 * LP * kb;
       if (b0 >= p) continue;
       double sgd[4];
       load4(a.sigma, true, b0, p, sgd);
@@ -459,16 +469,16 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
         }
       }
     }
-    lqr = -wave_sum(static_cast<double>(q));
+    lqr = -group_sum<LP>(static_cast<double>(q));
   }
   const double log_alpha = llp - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
   const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
                                 a.k0, a.k1);
   const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
-  const bool acc = log(u) < log_alpha;   // false for NaN; the same in every lane
+  const bool acc = log(u) < log_alpha;   // false for NaN; the same in every lane of the group
   if (acc) {
-    store_row(beta, lane, p, nv);
-    if constexpr (MALA) store_row(gl, lane, p, gnew);
+    store_row<LP>(beta, lane, p, nv);
+    if constexpr (MALA) store_row<LP>(gl, lane, p, gnew);
     if (lane == 0) a.ll[i] = llp;
   }
   if (lane == 0) a.acc_cnt[i] += acc ? 1 : 0;
@@ -484,7 +494,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
             gv[kb][k] = gnew[kb][k];
           }
       } else {
-        load_row(const_cast<const PT *>(gl), lane, p, gv);
+        load_row<LP>(const_cast<const PT *>(gl), lane, p, gv);
       }
     } else {
 #pragma unroll
@@ -495,7 +505,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
           gv[kb][k] = PT(0);
         }
     }
-    propose_row<P, PT, MALA>(na, i, lane, true, cur, gv);
+    propose_row<P, PT, MALA, LP>(na, i, lane, true, cur, gv);
   }
 }
 
@@ -866,44 +876,62 @@ void launch_pack_b(Prec prec, bool in_f64, const void *beta, int M, int M_pad, i
 #undef SPA_PACK
 }
 
+// Lanes per particle row of the proposal and decision kernels: half a wave when the
+// padded row fits in 256 markers.
+static inline int row_lanes(int PP) { return PP <= 256 ? 32 : 64; }
+
+template <Prec P, typename PT, bool MALA>
+static void launch_propose_t(const ProposeArgs &a, hipStream_t st) {
+  if (row_lanes(a.PP) == 32)
+    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32>), dim3(grid_rows(a.M_pad, 8)), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64>), dim3(grid_rows(a.M_pad, 4)), dim3(256), 0, st, a);
+}
+
 void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) {
-  const int grid = grid_rows(a.M_pad, 4);
-#define SPA_PROP(P, PT, MA) hipLaunchKernelGGL((propose_kernel<P, PT, MA>), dim3(grid), dim3(256), 0, st, a)
   if (prec == Prec::F64) {
-    if (mala) SPA_PROP(Prec::F64, double, true); else SPA_PROP(Prec::F64, double, false);
+    if (mala) launch_propose_t<Prec::F64, double, true>(a, st);
+    else launch_propose_t<Prec::F64, double, false>(a, st);
   } else if (prec == Prec::F32) {
-    if (mala) SPA_PROP(Prec::F32, float, true); else SPA_PROP(Prec::F32, float, false);
+    if (mala) launch_propose_t<Prec::F32, float, true>(a, st);
+    else launch_propose_t<Prec::F32, float, false>(a, st);
   } else {
-    if (mala) SPA_PROP(Prec::BF16X2, float, true); else SPA_PROP(Prec::BF16X2, float, false);
+    if (mala) launch_propose_t<Prec::BF16X2, float, true>(a, st);
+    else launch_propose_t<Prec::BF16X2, float, false>(a, st);
   }
-#undef SPA_PROP
 }
 
 template <Prec P, typename PT, bool MALA, bool NEXT>
-static void launch_accept_t(bool parts, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
-  const int grid = grid_rows(a.M, 4);
-  if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT>), dim3(grid), dim3(256), 0, st, a, na);
-  else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT>), dim3(grid), dim3(256), 0, st, a, na);
-}
-
-template <Prec P, typename PT>
-static void launch_accept_p(bool mala, bool parts, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
-  const ProposeArgs none{};
-  if (next) {
-    if (mala) launch_accept_t<P, PT, true, true>(parts, a, *next, st);
-    else launch_accept_t<P, PT, false, true>(parts, a, *next, st);
+static void launch_accept_t(bool parts, int PP, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
+  if (row_lanes(PP) == 32) {
+    const int grid = grid_rows(a.M, 8);
+    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 32>), dim3(grid), dim3(256), 0, st, a, na);
+    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 32>), dim3(grid), dim3(256), 0, st, a, na);
   } else {
-    if (mala) launch_accept_t<P, PT, true, false>(parts, a, none, st);
-    else launch_accept_t<P, PT, false, false>(parts, a, none, st);
+    const int grid = grid_rows(a.M, 4);
+    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 64>), dim3(grid), dim3(256), 0, st, a, na);
+    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 64>), dim3(grid), dim3(256), 0, st, a, na);
   }
 }
 
-void launch_accept(Prec prec, bool mala, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
+template <Prec P, typename PT>
+static void launch_accept_p(bool mala, bool parts, int PP, const AcceptArgs &a, const ProposeArgs *next,
+                            hipStream_t st) {
+  const ProposeArgs none{};
+  if (next) {
+    if (mala) launch_accept_t<P, PT, true, true>(parts, PP, a, *next, st);
+    else launch_accept_t<P, PT, false, true>(parts, PP, a, *next, st);
+  } else {
+    if (mala) launch_accept_t<P, PT, true, false>(parts, PP, a, none, st);
+    else launch_accept_t<P, PT, false, false>(parts, PP, a, none, st);
+  }
+}
+
+void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
   const bool parts = a.spl_part != nullptr;
-  if (prec == Prec::F64) launch_accept_p<Prec::F64, double>(mala, parts, a, next, st);
-  else if (prec == Prec::F32) launch_accept_p<Prec::F32, float>(mala, parts, a, next, st);
-  else if (next) launch_accept_p<Prec::BF16X2, float>(mala, parts, a, next, st);
-  else launch_accept_p<Prec::F32, float>(mala, parts, a, next, st);   // no operand written: one instance
+  if (prec == Prec::F64) launch_accept_p<Prec::F64, double>(mala, parts, PP, a, next, st);
+  else if (prec == Prec::F32 || !next) launch_accept_p<Prec::F32, float>(mala, parts, PP, a, next, st);
+  else launch_accept_p<Prec::BF16X2, float>(mala, parts, PP, a, next, st);   // no operand written: one instance
 }
 
 void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,

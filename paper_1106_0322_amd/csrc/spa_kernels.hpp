@@ -74,9 +74,10 @@ void launch_pack_b(Prec prec, bool in_f64, const void *beta, int M, int M_pad, i
                    const double *mu, const double *s, const double *inv_s, const double *ytil,
                    void *Bhi, void *Blo, double *moff, double *yb, hipStream_t st);
 void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st);
-// next != null: each wave also draws the next sweep's proposal (same buffers as a
-// launch_propose with *next) from the row it has just decided.
-void launch_accept(Prec prec, bool mala, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st);
+// next != null: the decision kernel also draws the next sweep's proposal (same buffers as
+// a launch_propose with *next) from each row it has just decided.  PP: the padded row
+// length of the contraction's operand (it sets the lanes per particle row).
+void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st);
 void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,
                      double lam_old, double *logw, hipStream_t st);
 void launch_lse_resample(const LseArgs &a, hipStream_t st);
