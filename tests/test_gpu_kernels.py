@@ -63,10 +63,13 @@ def test_loglik_parity(name, prec, M, tol):
     assert np.allclose(ref, likelihood.loglik(b, Xs, y))
 
 
-def test_loglik_fp8_storage_equals_bf16_storage():
+@pytest.mark.parametrize("n,p", [(2000, 50), (2000, 300)])
+def test_loglik_fp8_storage_equals_bf16_storage(n, p):
+    """The 0/1/2 genotypes are exact in FP8 and in BF16, and both storages feed the same
+    BF16 contraction (rows of up to 256 and of more markers): identical results."""
     torch = _torch()
-    s8, cfg, X, y, Xs = _sampler("cfg1", "bf16x2", xfmt="fp8")
-    s16, *_ = _sampler("cfg1", "bf16x2", xfmt="bf16")
+    s8, cfg, X, y, Xs = _sampler("cfg1", "bf16x2", n=n, p=p, xfmt="fp8")
+    s16, *_ = _sampler("cfg1", "bf16x2", n=n, p=p, xfmt="bf16")
     b = torch.from_numpy(particles(257, X.shape[1], seed=3)).to("cuda", torch.float32)
     assert torch.equal(s8.loglik(b), s16.loglik(b))
 
@@ -74,6 +77,9 @@ def test_loglik_fp8_storage_equals_bf16_storage():
 @pytest.mark.parametrize("n,p,prec,M", [
     (130, 1, "fp64", 1), (130, 1, "bf16x2", 65), (70, 7, "fp32", 129), (200, 255, "fp64", 17),
     (200, 511, "bf16x2", 33), (200, 511, "fp32", 40), (64, 31, "bf16x2", 64), (66, 32, "bf16x2", 3),
+    # BF16 rows of PP = 64, 128, 224, 256; one split (n <= 64) and ragged tails
+    (60, 100, "bf16x2", 50), (200, 63, "bf16x2", 129), (100, 127, "bf16x2", 5), (34, 200, "bf16x2", 130),
+    (300, 255, "bf16x2", 200),
 ])
 def test_loglik_edge_shapes(n, p, prec, M):
     torch = _torch()
@@ -122,6 +128,26 @@ def test_grad_parity(name, prec, M, lam):
         assert np.all(err <= tol)
         ltol = 1e-10 if prec == "fp64" else 1e-4
         assert rel_err(lp.cpu().numpy(), lp_ref).max() <= ltol
+
+
+@pytest.mark.parametrize("n,p,M", [(60, 100, 70), (66, 32, 3), (300, 255, 130), (1000, 200, 257)])
+def test_grad_parity_edge_shapes_bf16(n, p, M):
+    """The BF16 adjoint at one split (n <= 64), ragged tails, PP = 64, 224 and 256, and
+    particle counts that leave partial workgroups."""
+    torch = _torch()
+    s, cfg, X, y, Xs = _sampler("cfg3", "bf16x2", n=n, p=p)
+    b = particles(M, p, seed=n + 3 * p)
+    bt = torch.from_numpy(b).to("cuda", torch.float32)
+    bs = bt.double().cpu().numpy()
+    lam = 0.05
+    g, lp = s.grad(bt, lam, "bf16x2")
+    ll_ref, gl_ref = likelihood.loglik_and_grad(bs, Xs, y)
+    g_ref = gl_ref + gt_prior.gt_grad(bs, cfg.a, lam)
+    err = np.abs(g.double().cpu().numpy() - g_ref)
+    tol = _grad_tol("bf16x2", Xs) + 2.0 ** -24 * np.abs(g_ref)
+    print(f"n={n} p={p} M={M}: grad max abs err {err.max():.3e}")
+    assert np.all(err <= tol)
+    assert rel_err(lp.cpu().numpy(), ll_ref + gt_prior.log_prior(bs, cfg.a, lam)).max() <= 1e-4
 
 
 def test_grad_central_differences_fp64():
