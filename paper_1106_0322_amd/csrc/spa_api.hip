@@ -215,7 +215,9 @@ void tbeg(spa_smc *h, int cat) {
   const size_t k = 2 * h->ev_cat.size();
   while (h->ev.size() < k + 2) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) {
+    // timing only, read after a stream synchronisation: no system-scope fence (its cache
+    // write-back and invalidation would land on the bracketed kernels)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
       h->timing = false;
       return;
     }

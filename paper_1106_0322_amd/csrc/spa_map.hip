@@ -5,11 +5,13 @@
 // weighted-L1 logistic problem by cyclic coordinate ascent with the curvature bound n/4,
 // beta_j <- S(beta_j + 4 g_j / n, 4 w_j / n), g_j = sum_k (y_k - sigma(eta_k)) X_std,kj.
 //
-// One workgroup (4 wave64s) per start point.  Thread t keeps the linear predictor eta and
-// sigma(eta) of individuals t, t+256, ... in registers; the coefficients and weights live
+// One workgroup (16 wave64s) per start point.  Thread t keeps the linear predictor eta and
+// sigma(eta) of individuals t, t+1024, ... in registers; the coefficients and weights live
 // in LDS.  Each coordinate update is one block-wide reduction of g_j (wave sums, then the
-// four wave partials added in a fixed order by every thread, so all threads take the same
-// value) followed by a register update of eta and sigma when the coordinate moved.
+// 16 wave partials added in a fixed order by every thread, so all threads take the same
+// value) followed by a register update of eta and sigma when the coordinate moved.  The
+// updates of one start point are sequential, so its latency is set by the per-thread
+// column loads and the reduction: the widest workgroup keeps both short.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -20,7 +22,7 @@ namespace spa {
 
 namespace {
 
-constexpr int kMapThreads = 256;
+constexpr int kMapThreads = 1024;
 constexpr int kMapWaves = kMapThreads / 64;
 
 __device__ __forceinline__ double sigmoid(double e) { return 1.0 / (1.0 + exp(-e)); }
@@ -198,18 +200,18 @@ void launch_em_r(const MapArgs &a, hipStream_t st) {
 template <typename IT>
 hipError_t launch_em_t(const MapArgs &a, hipStream_t st) {
   const int R = (a.n_pad + kMapThreads - 1) / kMapThreads;
-  if (R <= 2) launch_em_r<IT, 2>(a, st);
+  if (R <= 1) launch_em_r<IT, 1>(a, st);
+  else if (R <= 2) launch_em_r<IT, 2>(a, st);
   else if (R <= 4) launch_em_r<IT, 4>(a, st);
-  else if (R <= 8) launch_em_r<IT, 8>(a, st);
-  else if (R <= 16) launch_em_r<IT, 16>(a, st);
-  else if (R <= 40) launch_em_r<IT, 40>(a, st);
+  else if (R <= 6) launch_em_r<IT, 6>(a, st);
+  else if (R <= 10) launch_em_r<IT, 10>(a, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 }  // namespace
 
-int map_max_n() { return kMapThreads * 40; }
+int map_max_n() { return kMapThreads * 10; }
 
 hipError_t launch_map_cols(const uint8_t *X, const uint8_t *y, int n, int p, int n_pad, const double *mu,
                            const double *sd, double *xs, double *yv, hipStream_t st) {
