@@ -95,6 +95,29 @@ def test_loglik_edge_shapes(n, p, prec, M):
     assert np.allclose(z, -n * math.log(2.0), rtol=1e-12 if prec == "fp64" else 1e-6)
 
 
+@pytest.mark.parametrize("name,prec", [("cfg3", "bf16x2"), ("cfg3", "fp32"), ("cfg1", "bf16x2"), ("cfg0", "fp64")])
+def test_loglik_difference_of_a_move(name, prec):
+    """The MH decision uses l(beta') - l(beta): its absolute error for proposal-sized moves
+    (the sum of the two evaluations' errors bounds it; both are checked to 1e-4 or 1e-10
+    relative), reported beside the per-particle errors."""
+    torch = _torch()
+    s, cfg, X, y, Xs = _sampler(name, prec)
+    M = 256
+    b = particles(M, X.shape[1], seed=11)
+    rng = np.random.default_rng(5)
+    b2 = b + 0.01 * rng.standard_normal(b.shape)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    bt, bt2 = (torch.from_numpy(v).to("cuda", dt) for v in (b, b2))
+    l1, l2 = s.loglik(bt, prec).cpu().numpy(), s.loglik(bt2, prec).cpu().numpy()
+    r1 = likelihood.loglik(bt.double().cpu().numpy(), Xs, y)
+    r2 = likelihood.loglik(bt2.double().cpu().numpy(), Xs, y)
+    err = np.abs((l2 - l1) - (r2 - r1))
+    rel = 1e-10 if prec == "fp64" else 1e-4
+    print(f"{name} {prec}: |d(l'-l)| max {err.max():.3e}, median {np.median(err):.3e}; "
+          f"|l'-l| median {np.median(np.abs(r2 - r1)):.3e}")
+    assert np.all(err <= rel * (np.abs(r1) + np.abs(r2)))
+
+
 def _grad_tol(prec, Xs):
     # FP64: round-off only.  Reduced precision: the coefficients enter as b~ = b (1 + d),
     # |d| <= 2^-16 (BF16 hi+lo) or 2^-24 (FP32), the residuals likewise, and the FP32
