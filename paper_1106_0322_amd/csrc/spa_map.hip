@@ -67,20 +67,34 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
     for (int j = tid; j < p; j += kMapThreads)
       wl[j] = pr.inf ? 1.0 / pr.lam : (pr.a + 1.0) / (pr.a * pr.lam + fabs(bl[j]));
     __syncthreads();
+    // up to 6 individuals per thread, column j+1 is loaded while coordinate j is reduced
+    // and updated (more would not fit the registers of a 1024-thread workgroup)
+    constexpr bool PF = R <= 6;
+    auto load_col = [&](const int j, double (&v)[R]) {
+      const double *c = xs + (size_t)j * n_pad;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int k = tid + kMapThreads * r;
+        v[r] = k < n_pad ? c[k] : 0.0;
+      }
+    };
     for (int sw = 0; sw < a.inner; ++sw) {
+      double xn[R];
+      if constexpr (PF) load_col(0, xn);
       for (int j = 0; j < p; ++j) {
-        const double *col = xs + (size_t)j * n_pad;
         // read beta_j before the barrier: thread 0 overwrites it after the barrier
         const double bj = bl[j], wj = wl[j];
         double x[R];
+        if constexpr (PF) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) x[r] = xn[r];
+          if (j + 1 < p) load_col(j + 1, xn);
+        } else {
+          load_col(j, x);
+        }
         double g = 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int k = tid + kMapThreads * r;
-          x[r] = k < n_pad ? col[k] : 0.0;
-          // padded individuals: x = 0, so they add nothing
-          g += (yk[r] - sg[r]) * x[r];
-        }
+        for (int r = 0; r < R; ++r) g += (yk[r] - sg[r]) * x[r];   // padded individuals: x = 0
         g = wave_sum(g);
         if (lane == 0) part[parity][wave] = g;
         __syncthreads();
