@@ -243,6 +243,15 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
         lds_dma16(bt_ + toff[q], smem + (stage_) * STG + XSL + q * NTHR + wave * 64);                   \
     }                                                                                                    \
   } while (0)
+  // One of the NQX + NQT copy instructions of a tile (part < NQX: individual-major copy).
+  auto issue_part = [&](const int tile0_, const int stage_, const int part) {
+    if (part < NQX) {
+      lds_dma16(gxk + (size_t)(tile0_) * PP * sizeof(XG) + xoff[part], smem + (stage_) * STG + part * NTHR + wave * 64);
+    } else if constexpr (GRAD) {
+      const int q = part - NQX;
+      lds_dma16(gxt + (size_t)(tile0_) * sizeof(XG) + toff[q], smem + (stage_) * STG + XSL + q * NTHR + wave * 64);
+    }
+  };
   // FP8 storage: each 16-byte chunk of codes becomes two BF16 chunks, through registers.
 #define SPA_COPY_FP8(tile0_, stage_)                                                                     \
   do {                                                                                                   \
@@ -282,10 +291,13 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
     constexpr bool MASKED = decltype(masked_c)::value;
     const int tile0 = i0 + it * NT;
     const int stage = it & 1;
-    if constexpr (!FP8) {
-      // unconditional: the last tile re-copies itself into the idle stage (never read)
-      SPA_ISSUE(i0 + min(it + 1, ntiles - 1) * NT, stage ^ 1);
-    }
+    // the next tile's copy; unconditional: the last tile re-copies itself into the idle
+    // stage (never read).  BF16: its instructions are spread over the first group's MFMA
+    // loops (one per forward k-step, one per other adjoint block) rather than issued in
+    // one burst, which stalls the wave's issue (measured: ~4 % of the kernel time).
+    const int ntile0 = i0 + min(it + 1, ntiles - 1) * NT;
+    constexpr bool SPREAD = (P == Prec::BF16X2) && !FP8 && (NKS >= NQX) && (NMB >= 2 * NQT);
+    if constexpr (!FP8 && !SPREAD) SPA_ISSUE(ntile0, stage ^ 1);
     const uint4 *sX = smem + stage * STG;          // individual-major tile, row stride CX slots
     const uint4 *sXt = sX + XSL;                   // marker-major tile, row stride CT slots
     // ---- per group of QB 16-individual blocks: forward -> elementwise -> adjoint
@@ -299,6 +311,9 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
         for (int pb = 0; pb < PB; ++pb) acc[b][pb] = AC{0, 0, 0, 0};
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
+        if constexpr (SPREAD) {
+          if (q == 0 && ks < NQX) issue_part(ntile0, stage ^ 1, ks);
+        }
 #pragma unroll
         for (int b = 0; b < QB; ++b) {
           const int ib = q * QB + b;
@@ -378,6 +393,9 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
             }
 #pragma unroll
           for (int mb = 0; mb < NMB; ++mb) {
+            if constexpr (SPREAD) {
+              if (q == 0 && (mb & 1) == 0 && mb / 2 < NQT) issue_part(ntile0, stage ^ 1, NQX + mb / 2);
+            }
             // the marker-major copy holds this lane group's 8 K slots contiguously
             const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sXt + (mb * 16 + lr) * CT + q * 4 + lg);
 #pragma unroll
