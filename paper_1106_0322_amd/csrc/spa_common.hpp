@@ -109,12 +109,17 @@ __device__ __forceinline__ double gt_grad(double b, const Prior &pr) {
 // instead of one per coefficient): log Gt(b) = -log(2c) - (a+1) log(1 + |b|/(a c)).
 template <typename T>
 __device__ __forceinline__ T gt_factor(T b, T inv_ac) { return T(1) + fabs(b) * inv_ac; }
+// x / y in the particle precision: FP64 divides; FP32 multiplies by the hardware
+// reciprocal (1 ulp), the proposal and decision arithmetic of the reduced-precision
+// sampler (deterministic, so the forward and reverse MALA densities use the same function).
+__device__ __forceinline__ double div_t(double x, double y) { return x / y; }
+__device__ __forceinline__ float div_t(float x, float y) { return x * __builtin_amdgcn_rcpf(y); }
 // d/db log Gt(b) = -(a+1) sign(b) / (a c + |b|); -sign(b)/c for the double exponential.
 template <typename T>
 __device__ __forceinline__ T gt_grad_t(T b, T a1, T ac, int inf, T inv_c) {
   const T sg = (b > T(0)) ? T(1) : ((b < T(0)) ? T(-1) : T(0));
   if (inf) return -sg * inv_c;
-  return -a1 * sg / (ac + fabs(b));
+  return div_t(-a1 * sg, ac + fabs(b));
 }
 __device__ __forceinline__ float fast_log(float x) { return __logf(x); }
 __device__ __forceinline__ double fast_log(double x) { return log(x); }

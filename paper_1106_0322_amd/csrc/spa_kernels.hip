@@ -301,7 +301,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
           const PT meanf = c + PT(0.5) * step * sg * sg * g;
           nv[k] = meanf + sqrt_step * sg * z[k];
           const PT d = nv[k] - meanf;
-          q += d * d / (PT(2) * step * sg * sg);
+          q += div_t(d * d, PT(2) * step * sg * sg);
         } else {
           nv[k] = c + step * sg * z[k];
         }
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
           const PT g = gnew[kb][k] + gt_grad_t<PT>(nv[kb][k], a1, ac, pr.inf, inv_c);
           const PT meanr = nv[kb][k] + PT(0.5) * step * sg * sg * g;
           const PT d = cur[kb][k] - meanr;
-          q += d * d / (PT(2) * step * sg * sg);
+          q += div_t(d * d, PT(2) * step * sg * sg);
         }
       }
     }
