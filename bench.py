@@ -6,7 +6,7 @@ contraction (+ adjoint for MALA) -> MH decisions) and weighted moments, over the
 particles of the workload.  The workload is the n=5000 / p=200 / N=16384 MALA run with
 BF16 hi+lo contractions (LD blocks of 20, a = 1, 100 scales, 10 sweeps per scale).
 
-    python bench.py [--steps K] [--warmup W] [--workload cfg3] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload n5000_p200_mala_bf16] [--no-cpu]
 
 Prints one JSON line.  `value` is whole-job algorithmic contraction throughput
 (2 N n p flops per log-likelihood evaluation plus 2 N n p per gradient evaluation)
@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1106_0322_amd/csrc/spa_gemm.hip", "paper_1106_0322_amd/csrc/spa_common.hpp",
                   "paper_1106_0322_amd/csrc/spa_internal.hpp"]
 BREAKDOWN_STEPS = 2       # untimed steps after the timed ones, every kernel class bracketed
-TRAFFIC_PROFILE = {"cfg3": "profiles/loglik_kernel_n5000_p200_N16384_mala_bf16x2_traffic.txt"}
+TRAFFIC_PROFILE = {"n5000_p200_mala_bf16": "profiles/loglik_kernel_n5000_p200_N16384_mala_bf16x2_traffic.txt"}
 
 
 def profiled_traffic(workload: str):
@@ -207,7 +207,7 @@ def ess_protocol(R: int = 8):
     divided by the wall-clock of one full sweep (init + T-1 steps)."""
     from synth import CONFIGS, make_dataset
 
-    mala, rwm = CONFIGS["cfg3"], CONFIGS["cfg3_rwm32"]
+    mala, rwm = CONFIGS["n5000_p200_mala_bf16"], CONFIGS["n5000_p200_rwm_fp32"]
     d = make_dataset(mala)
     ref_mean, ref_var, ref_logz, ref_s = full_sweep(mala, d.X, d.y, seed=9999, N=4 * mala.N,
                                                     sweeps=2 * mala.sweeps, prec="fp64")
@@ -238,7 +238,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg3")
+    ap.add_argument("--workload", default="n5000_p200_mala_bf16")
     ap.add_argument("--init-sweeps", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")

@@ -69,23 +69,23 @@ def lambda_grid(hi: float, lo: float, T: int) -> np.ndarray:
 
 
 CONFIGS = {
-    "cfg0": WorkloadConfig("cfg0", n=500, p=10, rho=0.90, block=0, k_causal=2, beta_sd=0.5,
+    "n500_p10_rwm_fp64": WorkloadConfig("n500_p10_rwm_fp64", n=500, p=10, rho=0.90, block=0, k_causal=2, beta_sd=0.5,
                            N=1024, T=20, a=1.0, move="rwm", sweeps=5, init_sweeps=200,
                            prec="fp64", seed=0, data_seed=0),
-    "cfg1": WorkloadConfig("cfg1", n=2000, p=50, rho=0.95, block=0, k_causal=3, beta_sd=0.3,
+    "n2000_p50_rwm_fp32": WorkloadConfig("n2000_p50_rwm_fp32", n=2000, p=50, rho=0.95, block=0, k_causal=3, beta_sd=0.3,
                            N=8192, T=100, a=0.5, move="rwm", sweeps=10, init_sweeps=200,
                            prec="fp32", seed=1, data_seed=1),
-    "cfg2": WorkloadConfig("cfg2", n=2000, p=50, rho=0.95, block=0, k_causal=3, beta_sd=0.3,
+    "n2000_p50_rwm_fp8": WorkloadConfig("n2000_p50_rwm_fp8", n=2000, p=50, rho=0.95, block=0, k_causal=3, beta_sd=0.3,
                            N=8192, T=100, a=0.5, move="rwm", sweeps=10, init_sweeps=200,
                            prec="bf16x2", xfmt="fp8", seed=1, data_seed=1),
-    "cfg3": WorkloadConfig("cfg3", n=5000, p=200, rho=0.97, block=20, k_causal=5, beta_sd=0.2,
+    "n5000_p200_mala_bf16": WorkloadConfig("n5000_p200_mala_bf16", n=5000, p=200, rho=0.97, block=20, k_causal=5, beta_sd=0.2,
                            N=16384, T=100, a=1.0, move="mala", sweeps=10, init_sweeps=500,
                            prec="bf16x2", xfmt="bf16", seed=3, data_seed=3),
-    "cfg4": WorkloadConfig("cfg4", n=10000, p=500, rho=0.97, block=25, k_causal=8, beta_sd=0.2,
+    "n10000_p500_mala_fp8": WorkloadConfig("n10000_p500_mala_fp8", n=10000, p=500, rho=0.97, block=25, k_causal=8, beta_sd=0.2,
                            N=32768, T=200, a=0.5, move="mala", sweeps=10, init_sweeps=500,
                            prec="bf16x2", xfmt="fp8", seed=4, data_seed=4),
     # plain FP32 random-walk SMC on the n=5000, p=200 data (the comparison form)
-    "cfg3_rwm32": WorkloadConfig("cfg3_rwm32", n=5000, p=200, rho=0.97, block=20, k_causal=5,
+    "n5000_p200_rwm_fp32": WorkloadConfig("n5000_p200_rwm_fp32", n=5000, p=200, rho=0.97, block=20, k_causal=5,
                                  beta_sd=0.2, N=16384, T=100, a=1.0, move="rwm", sweeps=10,
                                  init_sweeps=500, prec="fp32", seed=3, data_seed=3),
     # the paper's own shapes and kernel (Section 4.1: 5 cycles of single-coordinate random-walk

@@ -28,7 +28,7 @@ def _sampler(name, prec, n=None, p=None, N=64, xfmt="auto", move="rwm", T=2, **k
 
 def test_philox_bit_exact():
     torch = _torch()
-    s, *_ = _sampler("cfg0", "fp64")
+    s, *_ = _sampler("n500_p10_rwm_fp64", "fp64")
     rng = np.random.default_rng(0)
     ctr = rng.integers(0, 2 ** 32, size=(4096, 4), dtype=np.uint64)
     ctr[:3] = [[0, 0, 0, 0], [2 ** 32 - 1] * 4, [0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344]]
@@ -40,13 +40,13 @@ def test_philox_bit_exact():
 
 
 @pytest.mark.parametrize("name,prec,M,tol", [
-    ("cfg0", "fp64", 1000, 1e-10),
-    ("cfg1", "fp64", 333, 1e-10),
-    ("cfg1", "fp32", 700, 1e-4),
-    ("cfg1", "bf16x2", 700, 1e-4),
-    ("cfg3", "bf16x2", 300, 1e-4),
-    ("cfg3", "fp32", 200, 1e-4),
-    ("cfg3", "fp64", 100, 1e-10),
+    ("n500_p10_rwm_fp64", "fp64", 1000, 1e-10),
+    ("n2000_p50_rwm_fp32", "fp64", 333, 1e-10),
+    ("n2000_p50_rwm_fp32", "fp32", 700, 1e-4),
+    ("n2000_p50_rwm_fp32", "bf16x2", 700, 1e-4),
+    ("n5000_p200_mala_bf16", "bf16x2", 300, 1e-4),
+    ("n5000_p200_mala_bf16", "fp32", 200, 1e-4),
+    ("n5000_p200_mala_bf16", "fp64", 100, 1e-10),
 ])
 def test_loglik_parity(name, prec, M, tol):
     torch = _torch()
@@ -68,8 +68,8 @@ def test_loglik_fp8_storage_equals_bf16_storage(n, p):
     """The 0/1/2 genotypes are exact in FP8 and in BF16, and both storages feed the same
     BF16 contraction (rows of up to 256 and of more markers): identical results."""
     torch = _torch()
-    s8, cfg, X, y, Xs = _sampler("cfg1", "bf16x2", n=n, p=p, xfmt="fp8")
-    s16, *_ = _sampler("cfg1", "bf16x2", n=n, p=p, xfmt="bf16")
+    s8, cfg, X, y, Xs = _sampler("n2000_p50_rwm_fp32", "bf16x2", n=n, p=p, xfmt="fp8")
+    s16, *_ = _sampler("n2000_p50_rwm_fp32", "bf16x2", n=n, p=p, xfmt="bf16")
     b = torch.from_numpy(particles(257, X.shape[1], seed=3)).to("cuda", torch.float32)
     assert torch.equal(s8.loglik(b), s16.loglik(b))
 
@@ -83,7 +83,7 @@ def test_loglik_fp8_storage_equals_bf16_storage(n, p):
 ])
 def test_loglik_edge_shapes(n, p, prec, M):
     torch = _torch()
-    s, cfg, X, y, Xs = _sampler("cfg3", prec, n=n, p=p)
+    s, cfg, X, y, Xs = _sampler("n5000_p200_mala_bf16", prec, n=n, p=p)
     b = particles(M, p, seed=n + p)
     bt = torch.from_numpy(b).to("cuda", torch.float64)
     got = s.loglik(bt, prec).cpu().numpy()
@@ -95,7 +95,7 @@ def test_loglik_edge_shapes(n, p, prec, M):
     assert np.allclose(z, -n * math.log(2.0), rtol=1e-12 if prec == "fp64" else 1e-6)
 
 
-@pytest.mark.parametrize("name,prec", [("cfg3", "bf16x2"), ("cfg3", "fp32"), ("cfg1", "bf16x2"), ("cfg0", "fp64")])
+@pytest.mark.parametrize("name,prec", [("n5000_p200_mala_bf16", "bf16x2"), ("n5000_p200_mala_bf16", "fp32"), ("n2000_p50_rwm_fp32", "bf16x2"), ("n500_p10_rwm_fp64", "fp64")])
 def test_loglik_difference_of_a_move(name, prec):
     """The MH decision uses l(beta') - l(beta): its absolute error for proposal-sized moves
     (the sum of the two evaluations' errors bounds it; both are checked to 1e-4 or 1e-10
@@ -128,8 +128,8 @@ def _grad_tol(prec, Xs):
 
 
 @pytest.mark.parametrize("name,prec,M,lam", [
-    ("cfg0", "fp64", 300, 0.5), ("cfg3", "fp64", 64, 0.05), ("cfg3", "bf16x2", 256, 0.05),
-    ("cfg1", "fp32", 200, 2.0), ("cfg1", "bf16x2", 200, 1e-2),
+    ("n500_p10_rwm_fp64", "fp64", 300, 0.5), ("n5000_p200_mala_bf16", "fp64", 64, 0.05), ("n5000_p200_mala_bf16", "bf16x2", 256, 0.05),
+    ("n2000_p50_rwm_fp32", "fp32", 200, 2.0), ("n2000_p50_rwm_fp32", "bf16x2", 200, 1e-2),
 ])
 def test_grad_parity(name, prec, M, lam):
     torch = _torch()
@@ -158,7 +158,7 @@ def test_grad_parity_edge_shapes_bf16(n, p, M):
     """The BF16 adjoint at one split (n <= 64), ragged tails, PP = 64, 224 and 256, and
     particle counts that leave partial workgroups."""
     torch = _torch()
-    s, cfg, X, y, Xs = _sampler("cfg3", "bf16x2", n=n, p=p)
+    s, cfg, X, y, Xs = _sampler("n5000_p200_mala_bf16", "bf16x2", n=n, p=p)
     b = particles(M, p, seed=n + 3 * p)
     bt = torch.from_numpy(b).to("cuda", torch.float32)
     bs = bt.double().cpu().numpy()
@@ -177,7 +177,7 @@ def test_grad_central_differences_fp64():
     """The adjoint against central differences (h = 1e-6, FP64) on 64 particles of the
     n=5000, p=200 data, coefficients kept away from the prior's cusp."""
     torch = _torch()
-    s, cfg, X, y, Xs = _sampler("cfg3", "fp64")
+    s, cfg, X, y, Xs = _sampler("n5000_p200_mala_bf16", "fp64")
     rng = np.random.default_rng(11)
     b = rng.normal(0, 0.1, size=(64, X.shape[1]))
     b = np.where(np.abs(b) < 1e-4, 1e-4, b)
@@ -198,7 +198,7 @@ def test_grad_central_differences_fp64():
 def test_autograd_function_backward_is_the_adjoint():
     torch = _torch()
     from paper_1106_0322_amd import log_posterior
-    s, cfg, X, y, Xs = _sampler("cfg0", "fp64")
+    s, cfg, X, y, Xs = _sampler("n500_p10_rwm_fp64", "fp64")
     b = torch.from_numpy(particles(50, X.shape[1], seed=5)).cuda().requires_grad_(True)
     lp = log_posterior(b, 0.7, s, "fp64")
     w = torch.linspace(0.5, 2.0, 50, dtype=torch.float64, device="cuda")
@@ -211,7 +211,7 @@ def test_autograd_function_backward_is_the_adjoint():
 @pytest.mark.parametrize("M", [1, 2, 7, 64, 1000, 1024, 4097, 16384, 32768, 100000])
 def test_resample_bit_exact(M):
     torch = _torch()
-    s, *_ = _sampler("cfg0", "fp64")
+    s, *_ = _sampler("n500_p10_rwm_fp64", "fp64")
     rng = np.random.default_rng(M)
     for trial in range(4):
         w = rng.exponential(size=M) ** (1 + 3 * trial)
@@ -231,7 +231,7 @@ def test_resample_bit_exact(M):
 def test_resample_rejects_invalid_weights():
     torch = _torch()
     from paper_1106_0322_amd import SpaError
-    s, *_ = _sampler("cfg0", "fp64")
+    s, *_ = _sampler("n500_p10_rwm_fp64", "fp64")
     for w in ([0.0, 0.0], [1.0, -1.0], [1.0, float("nan")], [float("inf"), 1.0]):
         with pytest.raises(SpaError) as ei:
             s.resample(torch.tensor(w, dtype=torch.float64), 0)

@@ -26,11 +26,11 @@ def _handle(name, n=None, p=None, **over):
 
 
 @pytest.mark.parametrize("name,n,p,M,a,lam,outer,inner", [
-    ("cfg0", None, None, 7, 1.0, 0.05, 30, 5),
-    ("cfg0", None, None, 5, math.inf, 0.02, 10, 20),
-    ("cfg1", None, None, 6, 0.5, 0.1, 20, 4),
-    ("cfg3", 130, 150, 3, 4.0, 0.01, 10, 3),
-    ("cfg3", None, None, 2, 1.0, 0.02, 3, 2),
+    ("n500_p10_rwm_fp64", None, None, 7, 1.0, 0.05, 30, 5),
+    ("n500_p10_rwm_fp64", None, None, 5, math.inf, 0.02, 10, 20),
+    ("n2000_p50_rwm_fp32", None, None, 6, 0.5, 0.1, 20, 4),
+    ("n5000_p200_mala_bf16", 130, 150, 3, 4.0, 0.01, 10, 3),
+    ("n5000_p200_mala_bf16", None, None, 2, 1.0, 0.02, 3, 2),
 ])
 def test_map_em_matches_oracle(name, n, p, M, a, lam, outer, inner):
     torch = _torch()
@@ -54,7 +54,7 @@ def test_map_path_fp64_tracks_oracle():
     # enough iterations that the two EM runs of a scale, when they climb to the same mode,
     # agree far below the tolerance (their choice is then a tie decided by round-off)
     T, outer, inner = 8, 40, 10
-    s, cfg, X, y, Xs = _handle("cfg0")
+    s, cfg, X, y, Xs = _handle("n500_p10_rwm_fp64")
     r = smc.run_config(cfg, X, y, T_stop=T, snapshot_at=tuple(range(1, T + 1)))
     s.set_map(outer, inner)
     for _ in range(T - 1):
@@ -76,7 +76,7 @@ def test_map_path_fp64_tracks_oracle():
 def test_map_rejects_bad_arguments():
     torch = _torch()
     from paper_1106_0322_amd import SpaError
-    s, *_ = _handle("cfg0", N=64, lambdas=np.geomspace(10.0, 1.0, 3), init_sweeps=0, sweeps=0)
+    s, *_ = _handle("n500_p10_rwm_fp64", N=64, lambdas=np.geomspace(10.0, 1.0, 3), init_sweeps=0, sweeps=0)
     b = torch.zeros(2, 10, dtype=torch.float64, device="cuda")
     for lam, outer in ((0.0, 1), (-1.0, 1), (1.0, -1)):
         with pytest.raises(SpaError) as ei:

@@ -38,7 +38,7 @@ def _oracle_problem(cfg, X, y):
 @pytest.mark.parametrize("t", [8, 13, 14, 17])
 def test_one_step_weights_and_resampling_fp64(t):
     torch = _torch()
-    cfg, X, y, Xs = dataset("cfg0")
+    cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
     prob = _oracle_problem(cfg, X, y)
     lam = cfg.grid()
     res = smc.run_smc(prob, lam, cfg.N, "rwm", cfg.sweeps, cfg.init_sweeps, cfg.ess_frac,
@@ -71,7 +71,7 @@ def test_one_step_weights_and_resampling_fp64(t):
 
 def test_one_step_with_moves_fp64():
     torch = _torch()
-    cfg, X, y, Xs = dataset("cfg0")
+    cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
     prob = _oracle_problem(cfg, X, y)
     lam, t = cfg.grid(), 10
     res = smc.run_smc(prob, lam, cfg.N, "rwm", cfg.sweeps, cfg.init_sweeps, cfg.ess_frac,
@@ -99,7 +99,7 @@ def test_one_step_with_moves_fp64():
 
 
 def test_full_sweep_fp64_tracks_oracle():
-    cfg, X, y, Xs = dataset("cfg0")
+    cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
     r = smc.run_config(cfg, X, y)
     g = _gpu(cfg, X, y)
     stats = g.run()
@@ -121,17 +121,17 @@ def stat_compare(gpu, orc):
 
 
 @pytest.mark.parametrize("name,over,Rg,Ro", [
-    ("cfg1", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
-    ("cfg2", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
-    ("cfg3", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("n2000_p50_rwm_fp32", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("n2000_p50_rwm_fp8", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("n5000_p200_mala_bf16", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
 ])
 def test_statistical_parity(name, over, Rg, Ro):
     """Independent seeds on both sides; posterior means and log Z within MC error."""
-    cfg0 = CONFIGS[name].replace(**over)
-    n, p = (2000, 50) if name == "cfg3" else (None, None)
-    d = make_dataset(cfg0, n=n, p=p)
+    base = CONFIGS[name].replace(**over)
+    n, p = (2000, 50) if name == "n5000_p200_mala_bf16" else (None, None)
+    d = make_dataset(base, n=n, p=p)
     X, y = d.X, d.y
-    cfg = cfg0.replace(n=X.shape[0], p=X.shape[1])
+    cfg = base.replace(n=X.shape[0], p=X.shape[1])
     gm, gz, om, oz = [], [], [], []
     for r in range(Rg):
         g = _gpu(cfg, X, y, seed=1000 + r)
@@ -153,7 +153,7 @@ def test_statistical_parity(name, over, Rg, Ro):
 
 
 def test_determinism_same_seed():
-    cfg, X, y, Xs = dataset("cfg1")
+    cfg, X, y, Xs = dataset("n2000_p50_rwm_fp32")
     cfg = cfg.replace(N=2048, T=6, sweeps=3, init_sweeps=20, prec="bf16x2")
     paths = []
     for _ in range(2):
@@ -166,7 +166,7 @@ def test_determinism_same_seed():
 
 
 def test_timing_classes_bracket_only_the_named_kernels():
-    cfg, X, y, Xs = dataset("cfg1")
+    cfg, X, y, Xs = dataset("n2000_p50_rwm_fp32")
     cfg = cfg.replace(N=1024, T=6, sweeps=2, init_sweeps=2, prec="bf16x2", move="mala")
     g = _gpu(cfg, X, y)
     g.set_timing(True, classes=["loglik"])
@@ -188,7 +188,7 @@ def test_timing_classes_bracket_only_the_named_kernels():
     g.close()
 
 
-@pytest.mark.parametrize("name,init", [("cfg3", 4), ("cfg4", 2), ("cfg3_rwm32", 4)])
+@pytest.mark.parametrize("name,init", [("n5000_p200_mala_bf16", 4), ("n10000_p500_mala_fp8", 2), ("n5000_p200_rwm_fp32", 4)])
 def test_full_size_sampled_parity(name, init):
     """The live particle system at the full workload size and launch configuration:
     sampled particles' log-likelihoods (and gradients for MALA) against the oracle."""

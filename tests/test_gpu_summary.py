@@ -25,7 +25,7 @@ def _torch():
     return torch
 
 
-def _handle(name="cfg0", **over):
+def _handle(name="n500_p10_rwm_fp64", **over):
     from paper_1106_0322_amd import SamplerConfig, SpaSMC
     cfg, X, y, Xs = dataset(name)
     sc = SamplerConfig.from_workload(cfg, n=X.shape[0], p=X.shape[1], **over)
@@ -89,9 +89,9 @@ def test_weighted_summaries_edge_values_and_errors():
 
 
 def test_sampler_summaries_and_marginal_fp64_track_oracle():
-    """cfg0 FP64 for 10 scales: the per-scale summaries and the c-marginal mixture equal
+    """n500_p10_rwm_fp64 FP64 for 10 scales: the per-scale summaries and the c-marginal mixture equal
     the oracle's summaries of its own particle snapshots."""
-    cfg, X, y, Xs = dataset("cfg0")
+    cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
     T = 10
     r = smc.run_config(cfg, X, y, T_stop=T, snapshot_at=tuple(range(1, T + 1)))
     s, *_ = _handle()
@@ -126,7 +126,7 @@ def test_sampler_summaries_full_size_bf16():
     weights on both sides; the weights exponentiated on the host for the oracle, so only
     the last bit of each W may differ -- the test allows the quantised CDF that slack)."""
     torch = _torch()
-    s, cfg, X, y = _handle("cfg3", init_sweeps=20)
+    s, cfg, X, y = _handle("n5000_p200_mala_bf16", init_sweeps=20)
     s.set_summaries(LEVELS, DELTAS)
     s.step()
     q, c = s.summaries()
@@ -138,6 +138,6 @@ def test_sampler_summaries_full_size_bf16():
     cr = spa.concentration(b, W, DELTAS)
     dq = np.abs(q[-1] - qr)
     frac = np.mean(dq > 0)
-    print(f"cfg3 summaries: {frac:.4f} of quantiles differ, max |dV| {np.abs(c[-1] - cr).max():.3e}")
+    print(f"n5000_p200_mala_bf16 summaries: {frac:.4f} of quantiles differ, max |dV| {np.abs(c[-1] - cr).max():.3e}")
     assert frac <= 0.01
     assert np.abs(c[-1] - cr).max() <= 1e-12

@@ -10,7 +10,7 @@ from synth import CONFIGS, make_dataset
 
 
 def _data(n=200, p=8, seed=1):
-    cfg = CONFIGS["cfg0"].replace(k_causal=3, beta_sd=0.8)
+    cfg = CONFIGS["n500_p10_rwm_fp64"].replace(k_causal=3, beta_sd=0.8)
     d = make_dataset(cfg, n=n, p=p, seed=seed)
     Xs, _, _ = likelihood.standardise(d.X)
     return Xs, d.y.astype(np.float64)

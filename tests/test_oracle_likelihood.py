@@ -19,7 +19,7 @@ def small():
 
 
 def test_standardise_moments():
-    d = make_dataset(CONFIGS["cfg0"])
+    d = make_dataset(CONFIGS["n500_p10_rwm_fp64"])
     Xs, mu, s = likelihood.standardise(d.X)
     assert np.allclose(Xs.mean(axis=0), 0.0, atol=1e-14)
     assert np.allclose((Xs ** 2).mean(axis=0), 1.0, rtol=1e-13)     # population sd
@@ -33,7 +33,7 @@ def test_zero_variance_column_rejected():
 
 
 def test_beta_zero_is_minus_n_log2():
-    d = make_dataset(CONFIGS["cfg0"])
+    d = make_dataset(CONFIGS["n500_p10_rwm_fp64"])
     Xs, _, _ = likelihood.standardise(d.X)
     ll = likelihood.loglik(np.zeros((3, Xs.shape[1])), Xs, d.y)
     assert np.allclose(ll, -d.X.shape[0] * math.log(2.0), rtol=1e-15)
@@ -55,7 +55,7 @@ def test_bernoulli_product_brute_force(small):
 
 
 def test_label_flip_symmetry():
-    d = make_dataset(CONFIGS["cfg0"])
+    d = make_dataset(CONFIGS["n500_p10_rwm_fp64"])
     Xs, _, _ = likelihood.standardise(d.X)
     b = np.random.default_rng(4).normal(0, 0.3, size=(5, Xs.shape[1]))
     assert np.allclose(likelihood.loglik(-b, Xs, 1 - d.y), likelihood.loglik(b, Xs, d.y),
@@ -63,7 +63,7 @@ def test_label_flip_symmetry():
 
 
 def test_gradient_at_zero_closed_form():
-    d = make_dataset(CONFIGS["cfg0"])
+    d = make_dataset(CONFIGS["n500_p10_rwm_fp64"])
     Xs, _, _ = likelihood.standardise(d.X)
     g = likelihood.grad_loglik(np.zeros((1, Xs.shape[1])), Xs, d.y)[0]
     ref = np.array([sum(Xs[k, j] * (d.y[k] - 0.5) for k in range(Xs.shape[0]))
@@ -72,7 +72,7 @@ def test_gradient_at_zero_closed_form():
 
 
 def test_gradient_finite_differences():
-    d = make_dataset(CONFIGS["cfg0"])
+    d = make_dataset(CONFIGS["n500_p10_rwm_fp64"])
     Xs, _, _ = likelihood.standardise(d.X)
     rng = np.random.default_rng(5)
     b = rng.normal(0, 0.2, size=(4, Xs.shape[1]))

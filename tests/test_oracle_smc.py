@@ -47,7 +47,7 @@ def test_prior_only_targets_are_gt():
 
 
 def _tiny_dataset(p, seed):
-    cfg = CONFIGS["cfg0"].replace(k_causal=1, beta_sd=1.0, rho=0.5)
+    cfg = CONFIGS["n500_p10_rwm_fp64"].replace(k_causal=1, beta_sd=1.0, rho=0.5)
     d = make_dataset(cfg, n=60, p=p, seed=seed)
     Xs, _, _ = likelihood.standardise(d.X)
     return Xs, d.y.astype(np.float64)
@@ -80,7 +80,7 @@ def test_small_p_against_quadrature(p, move):
 
 def test_fixed_scale_mcmc_agrees_with_smc():
     """Section 4.2's check: run MCMC at a fixed intermediate scale and compare."""
-    cfg = CONFIGS["cfg0"]
+    cfg = CONFIGS["n500_p10_rwm_fp64"]
     d = make_dataset(cfg)
     Xs, _, _ = likelihood.standardise(d.X)
     prob = smc.Problem(Xs=Xs, y=d.y.astype(np.float64), a=cfg.a)
