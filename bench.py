@@ -33,14 +33,14 @@ KERNEL_SOURCES = ["paper_1106_0322_amd/csrc/spa_gemm.hip", "paper_1106_0322_amd/
                   "paper_1106_0322_amd/csrc/spa_internal.hpp"]
 BREAKDOWN_STEPS = 2       # untimed steps after the timed ones, every kernel class bracketed
 TRAFFIC_PROFILE = {"n5000_p200_mala_bf16": "profiles/loglik_kernel_n5000_p200_N16384_mala_bf16x2_traffic.txt"}
+MFMA_PROFILE = {"n5000_p200_mala_bf16": "profiles/loglik_kernel_n5000_p200_N16384_mala_bf16x2_mfma.txt"}
 
 
-def profiled_traffic(workload: str):
-    """HBM bytes per launch of the contraction kernel from the committed FETCH_SIZE /
-    WRITE_SIZE summary (copy-calibrated), or None when there is none for this workload or
-    the kernel source has changed since it was taken."""
+def profile_values(table: dict, workload: str):
+    """key=value lines of a committed counter summary for this workload, or None when there
+    is none or the contraction kernel's sources have changed since it was taken."""
     import hashlib
-    path = TRAFFIC_PROFILE.get(workload)
+    path = table.get(workload)
     if path is None or not os.path.exists(os.path.join(ROOT, path)):
         return None
     h = hashlib.sha256()
@@ -54,7 +54,14 @@ def profiled_traffic(workload: str):
             kv[k] = v
     if kv.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
         return None
-    return int(kv["hbm_bytes_per_launch"])
+    return kv
+
+
+def profiled_traffic(workload: str):
+    """HBM bytes per launch of the contraction kernel from the committed FETCH_SIZE /
+    WRITE_SIZE summary (copy-calibrated), or None (no summary, or stale)."""
+    kv = profile_values(TRAFFIC_PROFILE, workload)
+    return None if kv is None else int(kv["hbm_bytes_per_launch"])
 
 
 def copy_calibration():
@@ -291,6 +298,10 @@ def main():
     gemm_ms, gemm_n = tim["loglik"]
     gemm_avg_ms = gemm_ms / max(gemm_n, 1)
     achieved = gemm_flops(cfg) / (gemm_avg_ms * 1e-3) / 1e12
+    # executed matrix work (hi and lo products over the padded shapes) from the committed
+    # counter summary, over this run's live launch time; and the counters' pipe-busy share
+    mf = profile_values(MFMA_PROFILE, args.workload)
+    executed = None if mf is None else float(mf["mfma_flops_per_launch"]) / (gemm_avg_ms * 1e-3) / 1e12
     dtype = {"bf16x2": "bf16", "fp32": "f32", "fp64": "f64"}[cfg.prec]
     peak = PEAK[cfg.prec]
     out = {
@@ -315,7 +326,10 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": profiled_traffic(args.workload),
                      "kernel": "loglik_kernel (fused log-likelihood + adjoint)" if cfg.move == "mala"
-                     else "loglik_kernel", "avg_launch_us": round(gemm_avg_ms * 1e3, 2)},
+                     else "loglik_kernel", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
+                     "executed_TFLOPs": None if executed is None else round(executed, 2),
+                     "executed_frac": None if executed is None else round(executed / peak, 4),
+                     "mfma_busy_frac": None if mf is None else float(mf["mfma_busy_frac"])},
         "kernel_ms_per_step": {k: round(v[0] / BREAKDOWN_STEPS, 4) for k, v in brk.items()},
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
