@@ -960,7 +960,8 @@ void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void
                        (float *)dst, (const float *)gsrc, (float *)gdst, llsrc, lldst);
 }
 
-int moments_chunks(int M) { return std::max(1, (M + 255) / 256); }
+// 64-row chunks: 4 row groups of 16 rows per workgroup (N/64 x p/64 workgroups)
+int moments_chunks(int M) { return std::max(1, (M + 63) / 64); }
 
 void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
                     double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st) {
