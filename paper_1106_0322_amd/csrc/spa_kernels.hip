@@ -595,6 +595,7 @@ __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
       const double v = lw[i] - L;
       lw[i] = v;
       const double W = exp(v);
+      a.cdf[i] = W;   // kept for the resampling passes (same values, one exp per weight)
       s2 += W * W;
     }
     s2 = block_sum(s2, sh);
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
   double wmax = -INFINITY;
   int badw = 0;
   for (int i = lo; i < hi; ++i) {
-    const double w = (a.mode == 0) ? exp(lw[i]) : wsrc[i];
+    const double w = (a.mode == 0) ? a.cdf[i] : wsrc[i];
     if (!(w >= 0.0) || isinf(w)) badw = 1;
     wmax = fmax(wmax, w);
   }
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
   // ---- local inclusive sums of the quantised weights, then an exclusive block scan
   double run = 0.0;
   for (int i = lo; i < hi; ++i) {
-    const double w = (a.mode == 0) ? exp(lw[i]) : wsrc[i];
+    const double w = (a.mode == 0) ? a.cdf[i] : wsrc[i];
     run += floor((w / wmax) * scale);
     a.cdf[i] = run;
   }
@@ -649,16 +650,33 @@ __global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
   // ---- offspring positions and binary search (no fused multiply-add)
   const double U = static_cast<double>(a.u32) * 0x1p-32;
   const double dM = static_cast<double>(M);
+  // The positions increase with i and a thread owns a contiguous block of offspring, so
+  // each search starts at the previous offspring's index and gallops forward (probes at
+  // distances 1, 2, 4, ...), then bisects the last interval: the same first index k with
+  // cdf[k] > t, in O(log distance) loads.
+  int k = 0;
   for (int i = lo; i < hi; ++i) {
     const double num = __dadd_rn(static_cast<double>(i), U);
     const double tpos = __ddiv_rn(__dmul_rn(num, C), dM);
-    int l = 0, r = M;   // first k with cdf[k] > tpos
-    while (l < r) {
-      const int mid = (l + r) >> 1;
-      if (a.cdf[mid] > tpos) r = mid;
-      else l = mid + 1;
+    if (k < M && !(a.cdf[k] > tpos)) {
+      int below = k, above = M, step = 1;   // cdf[below] <= tpos; cdf[above] > tpos or above = M
+      while (below + step < M) {
+        if (a.cdf[below + step] > tpos) {
+          above = below + step;
+          break;
+        }
+        below += step;
+        step <<= 1;
+      }
+      int l = below + 1, r = above;
+      while (l < r) {
+        const int mid = (l + r) >> 1;
+        if (a.cdf[mid] > tpos) r = mid;
+        else l = mid + 1;
+      }
+      k = l;
     }
-    a.anc[i] = min(l, M - 1);
+    a.anc[i] = min(k, M - 1);
   }
   if (a.mode == 0) {
     const double lN = -log(dM);
