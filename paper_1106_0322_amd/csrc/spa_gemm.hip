@@ -270,6 +270,58 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
       }                                                                                                  \
     }                                                                                                    \
   } while (0)
+  // FP8 storage, in two halves: the next tile's codes are loaded into registers at the
+  // start of a tile (their latency hidden by the tile's MFMA work) and widened into the
+  // idle stage at its end.
+  constexpr int NFX = FP8 ? (NT * PP / 16 + NTHR - 1) / NTHR : 1;        // chunks per thread
+  constexpr int NFT = (FP8 && GRAD) ? (PP * NT / 16 + NTHR - 1) / NTHR : 1;
+  uint4 fx[NFX], ft[NFT];
+  auto fp8_load = [&](const int tile0_) {
+    if constexpr (FP8) {
+#pragma unroll
+      for (int u = 0; u < NFX; ++u) {
+        const int c = tid + u * NTHR;
+        if (c < NT * PP / 16) {
+          const int r = c / (PP / 16), cc = c % (PP / 16);
+          fx[u] = *reinterpret_cast<const uint4 *>(gxk + (size_t)(tile0_ + r) * PP + cc * 16);
+        }
+      }
+      if constexpr (GRAD) {
+#pragma unroll
+        for (int u = 0; u < NFT; ++u) {
+          const int c = tid + u * NTHR;
+          if (c < PP * NT / 16) {
+            const int r = c / (NT / 16), cc = c % (NT / 16);
+            ft[u] = *reinterpret_cast<const uint4 *>(gxt + (size_t)r * n_pad + tile0_ + cc * 16);
+          }
+        }
+      }
+    }
+  };
+  auto fp8_store = [&](const int stage_) {
+    if constexpr (FP8) {
+      __bf16 *sx_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG);
+#pragma unroll
+      for (int u = 0; u < NFX; ++u) {
+        const int c = tid + u * NTHR;
+        if (c < NT * PP / 16) {
+          const int r = c / (PP / 16), cc = c % (PP / 16);
+          store_fp8_as_bf16(sx_ + (r * CX + 2 * cc) * 8, fx[u]);
+        }
+      }
+      if constexpr (GRAD) {
+        __bf16 *st_ = reinterpret_cast<__bf16 *>(smem + (stage_) * STG + XSL);
+#pragma unroll
+        for (int u = 0; u < NFT; ++u) {
+          const int c = tid + u * NTHR;
+          if (c < PP * NT / 16) {
+            const int r = c / (NT / 16), cc = c % (NT / 16);
+            store_fp8_as_bf16(st_ + (r * CT + 2 * cc) * 8, ft[u]);
+          }
+        }
+      }
+    }
+  };
   // Wait for this thread's copies, then make every wave's copies visible.
 #define SPA_LAND()                                  \
   do {                                              \
@@ -296,6 +348,9 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
     // loops (one per forward k-step, one per other adjoint block) rather than issued in
     // one burst, which stalls the wave's issue (measured: ~4 % of the kernel time).
     const int ntile0 = i0 + min(it + 1, ntiles - 1) * NT;
+    if constexpr (FP8) {
+      if (it + 1 < ntiles) fp8_load(ntile0);
+    }
     constexpr bool SPREAD = (P == Prec::BF16X2) && !FP8 && (NKS >= NQX) && (NMB >= 2 * NQT);
     if constexpr (!FP8 && !SPREAD) SPA_ISSUE(ntile0, stage ^ 1);
     const uint4 *sX = smem + stage * STG;          // individual-major tile, row stride CX slots
@@ -431,7 +486,7 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
     }
 
     if constexpr (FP8) {
-      if (it + 1 < ntiles) SPA_COPY_FP8(tile0 + NT, stage ^ 1);
+      if (it + 1 < ntiles) fp8_store(stage ^ 1);
     }
     SPA_LAND();
   };
