@@ -28,8 +28,9 @@ definition it cites:
                     scale and the c-marginal mixture (Section 4, eq. all_particles).
 
 Parity status: every function here is pinned by the CPU tests (closed forms,
-library special cases, invariants, brute force, published known-answer vectors);
-posterior-mean paths at p >= 10 are pinned only statistically (there is no closed
-form), see the test-suite.
+library special cases, invariants, brute force, published known-answer vectors).  The
+sampler's posterior-mean and log-Z paths at p >= 10 have no closed form: there they are
+parity unpinned beyond the pins of the same code at p = 1, 2 and prior-only targets, and
+the GPU is compared with them statistically (replicate seeds), see the test-suite.
 """
 from . import gt_prior, likelihood, philox, smc, quadrature, spa, em  # noqa: F401
