@@ -54,9 +54,14 @@ typedef enum {
 typedef enum {
   SPA_PREC_FP64 = 0,    /* FP64 MFMA, FP64 elementwise: per-particle loglik rel. err ~1e-13 */
   SPA_PREC_FP32 = 1,    /* FP32 MFMA, FP32 elementwise, FP64 cross-tile sums: ~1e-6        */
-  SPA_PREC_BF16X2 = 2   /* genotypes exact in BF16 (or FP8 storage), beta/s split into BF16
+  SPA_PREC_BF16X2 = 2,  /* genotypes exact in BF16 (or FP8 storage), beta/s split into BF16
                            hi + lo parts, residuals likewise, FP32 MFMA accumulation:
                            per-particle loglik rel. err < 1e-4                             */
+  SPA_PREC_FP8X3 = 3,   /* forward log-likelihood only (spa_smc_loglik): genotypes exact in
+                           e4m3, beta/s split into 3 e4m3 terms with per-particle power-of-
+                           two scales (the block scales of the FP8 MFMA), FP32 accumulation:
+                           per-particle loglik rel. err < 1e-4; p <= 512                   */
+  SPA_PREC_FP8X4 = 4    /* as SPA_PREC_FP8X3 with 4 terms: rel. err below the BF16X2 one    */
 } spa_prec;
 
 /* Storage of the 0/1/2 genotype operand on the BF16X2 path (exact in both formats);
@@ -80,8 +85,9 @@ typedef struct {
   double step0;           /* initial random-walk kappa or MALA h, > 0                    */
   int32_t adapt;          /* 1: log step += clip(acceptance - target, -log 2, log 2) after
                              each burn-in sweep and each scale; 0: fixed step            */
-  spa_prec prec;          /* GEMM precision of the moves; particles are stored in FP64
-                             for SPA_PREC_FP64 and in FP32 otherwise                      */
+  spa_prec prec;          /* GEMM precision of the moves (FP64, FP32 or BF16X2; the FP8
+                             multi-term ones are for spa_smc_loglik only); particles are
+                             stored in FP64 for SPA_PREC_FP64 and in FP32 otherwise       */
   spa_xfmt xfmt;          /* genotype storage for SPA_PREC_BF16X2                         */
   uint64_t seed;          /* Philox4x32-10 key (low word, high word)                      */
 } spa_smc_config;
@@ -130,8 +136,14 @@ spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out);
  * spa_smc_loglik -- log f(y | X, beta_i) for M particles (Section 2 likelihood):
  * sum_k [y_k eta_ik - log(1 + exp(eta_ik))], eta_i = X_std beta_i.
  * beta_dev: M x p, FP64 if beta_is_fp64 else FP32.  loglik_dev: M doubles (output).
- * prec selects the contraction precision.  Asynchronous on the handle's stream.
- * Errors: SPA_ERR_ARG (null pointers, M < 1, bad prec).
+ * prec selects the contraction precision; the FP8 multi-term precisions (SPA_PREC_FP8X3,
+ * SPA_PREC_FP8X4) are served here only: the coefficient row of each particle is written as
+ * sum_t 2^E_t q_t with e4m3 entries q_t, term t taking the residual of the terms before it
+ * scaled so that its largest entry lies in [128, 256) (Section 2 likelihood on the
+ * represented coefficients, whose offsets and X_std^T y term are formed exactly in FP64).
+ * A particle with a non-finite coefficient gets a NaN log-likelihood.  Asynchronous on the
+ * handle's stream.
+ * Errors: SPA_ERR_ARG (null pointers, M < 1, bad prec, p > 255 with SPA_PREC_FP64).
  */
 spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
                           spa_prec prec, double *loglik_dev);
@@ -284,10 +296,11 @@ spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uin
 /*
  * Kernel timing.  spa_smc_set_timing(h, 1) resets the counters and brackets every
  * subsequent launch of spa_smc_step (and of the burn-in) with HIP events on the handle's
- * stream; spa_smc_get_timing fills ms[c] (total milliseconds) and launches[c] for the
- * SPA_TIMING_CLASSES classes below (launches of the burn-in, spa_smc_step,
- * spa_smc_loglik and spa_smc_grad).  Timing adds a few microseconds of event records per
- * launch; it is off by default.  Errors: SPA_ERR_ARG (null pointers).
+ * stream; spa_smc_get_timing synchronises that stream, collects every bracketed launch so
+ * far and fills ms[c] (total milliseconds) and launches[c] for the SPA_TIMING_CLASSES
+ * classes below (launches of the burn-in, spa_smc_step, spa_smc_loglik and spa_smc_grad).
+ * Timing adds a few microseconds of event records per launch; it is off by default.
+ * Errors: SPA_ERR_ARG (null pointers), SPA_ERR_HIP.
  */
 enum {
   SPA_T_PROPOSE = 0,    /* proposal + scaled-coefficient operand (first sweep of a   */
@@ -305,7 +318,7 @@ enum {
   SPA_TIMING_CLASSES = 10
 };
 spa_status spa_smc_set_timing(spa_smc *h, int32_t enable);
-spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches);
+spa_status spa_smc_get_timing(spa_smc *h, double *ms, int64_t *launches);
 
 /*
  * Timing of chosen classes only: bit c of class_mask brackets the launches of class c

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libspa_smc.so")
 SPA_OK, SPA_ERR_ARG, SPA_ERR_SHAPE, SPA_ERR_ALLOC, SPA_ERR_HIP, SPA_ERR_STATE, SPA_ERR_NUMERIC = range(7)
 STATUS_NAMES = ["SPA_OK", "SPA_ERR_ARG", "SPA_ERR_SHAPE", "SPA_ERR_ALLOC", "SPA_ERR_HIP",
                 "SPA_ERR_STATE", "SPA_ERR_NUMERIC"]
-PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x2": 2, "fp8x3": 3, "fp8x4": 4}
 XFMT = {"auto": 0, "fp8": 1, "bf16": 2}
 MOVE = {"rwm": 0, "mala": 1, "single": 2}
 

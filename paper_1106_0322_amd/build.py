@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspa_smc.so")
-SOURCES = ["spa_gemm.hip", "spa_kernels.hip", "spa_summary.hip", "spa_single.hip", "spa_map.hip",
+SOURCES = ["spa_gemm.hip", "spa_gemm_fp8x.hip", "spa_kernels.hip", "spa_summary.hip", "spa_single.hip", "spa_map.hip",
            "spa_api.hip"]
 ARCH = "gfx950"
 

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/spa_smc.h"
+#include "spa_gemm_fp8x.hpp"
 #include "spa_internal.hpp"
 #include "spa_kernels.hpp"
 #include "spa_map.hpp"
@@ -110,6 +111,13 @@ struct spa_smc {
   size_t g_part_cap = 0;
   double *llscr = nullptr;
   size_t llscr_cap = 0;
+  // FP8 multi-term forward contraction (loglik calls only)
+  uint8_t *f8_X = nullptr;       // n_pad x f8_PP genotype codes
+  int f8_PP = 0;
+  uint8_t *f8_Bq = nullptr;      // 4 x f8_cap x f8_PP term codes
+  int32_t *f8_Bs = nullptr;      // 4 x f8_cap term exponents
+  double *f8_moff = nullptr, *f8_yb = nullptr, *f8_part = nullptr;
+  size_t f8_cap = 0;             // particle rows of the buffers above
   std::vector<void *> allocs;
   // optional per-kernel-class timing with HIP events on the handle's stream
   bool timing = false;
@@ -944,10 +952,65 @@ static spa_status prep_operand(spa_smc *h, const void *beta, int M, int is_f64, 
 
 static bool valid_prec(spa_prec p) { return p == SPA_PREC_FP64 || p == SPA_PREC_FP32 || p == SPA_PREC_BF16X2; }
 
+// Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
+static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out) {
+  spa_status st;
+  const int PP = fp8x_pad_markers(h->p);
+  if (PP < 0) return set_err(h, SPA_ERR_ARG, "FP8 multi-term path needs p <= 512");
+  if (!h->f8_X) {
+    if ((st = dalloc(h, &h->f8_X, (size_t)h->n_pad * PP)) != SPA_OK) return st;
+    SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, h->n_pad, PP, h->f8_X, h->stream));
+    h->f8_PP = PP;
+  }
+  const int Mpad = round_up(M, kPartPad);
+  const int S = fp8x_splits(PP, h->n_pad, M);
+  if (h->f8_cap < (size_t)Mpad) {
+    dfree(h, h->f8_Bq);
+    dfree(h, h->f8_Bs);
+    dfree(h, h->f8_moff);
+    dfree(h, h->f8_yb);
+    dfree(h, h->f8_part);
+    h->f8_Bq = nullptr;
+    h->f8_Bs = nullptr;
+    h->f8_moff = h->f8_yb = h->f8_part = nullptr;
+    h->f8_cap = 0;
+    if ((st = dalloc(h, &h->f8_Bq, 4 * (size_t)Mpad * PP)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_Bs, 4 * 4 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_moff, 8 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_yb, 8 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_part, 8 * 8 * (size_t)Mpad)) != SPA_OK) return st;
+    h->f8_cap = Mpad;
+  }
+  SPA_CK(h, launch_fp8x_pack_b(nterm, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil,
+                               h->f8_Bq, h->f8_Bs, h->f8_moff, h->f8_yb, h->stream));
+  Fp8xArgs a{};
+  a.nterm = nterm;
+  a.PP = PP;
+  a.Xf = h->f8_X;
+  a.Bq = h->f8_Bq;
+  a.Bs = h->f8_Bs;
+  a.moff = h->f8_moff;
+  a.yb = h->f8_yb;
+  a.n = h->n;
+  a.n_pad = h->n_pad;
+  a.M = M;
+  a.M_pad = Mpad;
+  a.S = S;
+  a.spl_part = h->f8_part;
+  a.ll = out;
+  tbeg(h, SPA_T_LOGLIK);
+  const hipError_t e = launch_fp8x_loglik(a, h->stream);
+  tend(h);
+  SPA_CK(h, e);
+  return SPA_OK;
+}
+
 extern "C" spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
                                      spa_prec prec, double *loglik_dev) {
   if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
   if (!beta_dev || !loglik_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  if (prec == SPA_PREC_FP8X3 || prec == SPA_PREC_FP8X4)
+    return fp8x_loglik(h, beta_dev, M, beta_is_fp64, prec == SPA_PREC_FP8X3 ? 3 : 4, loglik_dev);
   if (!valid_prec(prec)) return set_err(h, SPA_ERR_ARG, "bad prec");
   if (prec == SPA_PREC_FP64 && h->p > 255) return set_err(h, SPA_ERR_ARG, "FP64 path needs p <= 255");
   const Prec P = to_prec(prec);
@@ -1234,8 +1297,10 @@ extern "C" spa_status spa_smc_set_timing_classes(spa_smc *h, uint32_t class_mask
   return SPA_OK;
 }
 
-extern "C" spa_status spa_smc_get_timing(const spa_smc *h, double *ms, int64_t *launches) {
+extern "C" spa_status spa_smc_get_timing(spa_smc *h, double *ms, int64_t *launches) {
   if (!h || !ms || !launches) return SPA_ERR_ARG;
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
   for (int c = 0; c < SPA_TIMING_CLASSES; ++c) {
     ms[c] = h->t_ms[c];
     launches[c] = h->t_cnt[c];
