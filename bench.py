@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK = {"bf16x2": 2500.0, "fp32": 157.3, "fp64": 78.6}     # dense MFMA TFLOP/s of MI355X
+PEAK_FP8 = 5000.0                                            # dense FP8 MFMA TFLOP/s of MI355X
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1106_0322_amd/csrc/spa_gemm.hip", "paper_1106_0322_amd/csrc/spa_common.hpp",
                   "paper_1106_0322_amd/csrc/spa_internal.hpp"]
@@ -149,6 +150,43 @@ def analysis_legs(torch, s, cfg):
                        "what": f"EM from 2 start points, 50 E steps x 5 coordinate sweeps, n={cfg.n} p={cfg.p}"}}
 
 
+def precision_legs(torch, s, cfg, reps: int = 20):
+    """The forward contraction (log-likelihood only) on the workload's live particles at
+    each reduced precision: BF16 hi+lo MFMA against the FP8 MFMA with the coefficients in 3
+    and 4 e4m3 terms.  Kernel time per call from the HIP events of the contraction and the
+    split combination; the call time adds the operand packing and launch overheads; the
+    deviation is the largest relative difference from the FP64 contraction on the same
+    particles."""
+    beta, _ = s.particles()
+    ref = s.loglik(beta.double(), "fp64").cpu().numpy() if cfg.p <= 255 else None
+    flops = 2.0 * beta.shape[0] * cfg.n * cfg.p
+    pp8 = -(-cfg.p // 128) * 128
+    out = {"what": f"forward contraction, N={beta.shape[0]} live particles, n={cfg.n} p={cfg.p}"}
+    for prec in ("bf16x2", "fp8x3", "fp8x4"):
+        ll = s.loglik(beta, prec).cpu().numpy()
+        s.set_timing(True, classes=["loglik", "finalize"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            s.loglik(beta, prec)
+        torch.cuda.synchronize()
+        call_s = (time.perf_counter() - t0) / reps
+        t = s.timing()
+        s.set_timing(False)
+        k_s = (t["loglik"][0] + t["finalize"][0]) / reps * 1e-3
+        rec = {"kernel_us": round(k_s * 1e6, 2), "call_us": round(call_s * 1e6, 2),
+               "algorithmic_TFLOPs": round(flops / k_s / 1e12, 2),
+               "max_rel_dev_vs_fp64": None if ref is None else float(f"{np.max(np.abs(ll - ref) / np.abs(ref)):.3e}")}
+        if prec.startswith("fp8x"):
+            terms = int(prec[-1])
+            n_pad = -(-cfg.n // 128) * 128
+            executed = 2.0 * beta.shape[0] * n_pad * pp8 * terms
+            rec["executed_TFLOPs"] = round(executed / k_s / 1e12, 2)
+            rec["executed_frac_of_fp8_peak"] = round(executed / k_s / 1e12 / PEAK_FP8, 4)
+        out[prec] = rec
+    return out
+
+
 def gemm_flops(cfg) -> float:
     """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
     f = 2.0 * cfg.N * cfg.n * cfg.p
@@ -251,6 +289,8 @@ def main():
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")
     ap.add_argument("--ess-seeds", type=int, default=8)
     ap.add_argument("--no-single", action="store_true", help="skip the single-coordinate kernel leg")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the forward-contraction comparison of BF16 hi+lo and the FP8 splits")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference "
                          "launch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -334,6 +374,8 @@ def main():
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
     out["analysis"] = analysis_legs(torch, s, cfg)
+    if not args.no_precision:
+        out["precision_variants"] = precision_legs(torch, s, cfg)
     s.close()
     if not args.no_single:
         out["single_site"] = single_site_leg()

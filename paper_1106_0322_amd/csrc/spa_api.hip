@@ -112,7 +112,7 @@ struct spa_smc {
   double *llscr = nullptr;
   size_t llscr_cap = 0;
   // FP8 multi-term forward contraction (loglik calls only)
-  uint8_t *f8_X = nullptr;       // n_pad x f8_PP genotype codes
+  uint8_t *f8_X = nullptr;       // (n rounded up to kF8Tile) x f8_PP genotype codes
   int f8_PP = 0;
   uint8_t *f8_Bq = nullptr;      // 4 x f8_cap x f8_PP term codes
   int32_t *f8_Bs = nullptr;      // 4 x f8_cap term exponents
@@ -957,13 +957,14 @@ static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, i
   spa_status st;
   const int PP = fp8x_pad_markers(h->p);
   if (PP < 0) return set_err(h, SPA_ERR_ARG, "FP8 multi-term path needs p <= 512");
+  const int n_pad = round_up(h->n, kF8Tile);
   if (!h->f8_X) {
-    if ((st = dalloc(h, &h->f8_X, (size_t)h->n_pad * PP)) != SPA_OK) return st;
-    SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, h->n_pad, PP, h->f8_X, h->stream));
+    if ((st = dalloc(h, &h->f8_X, (size_t)n_pad * PP)) != SPA_OK) return st;
+    SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
     h->f8_PP = PP;
   }
   const int Mpad = round_up(M, kPartPad);
-  const int S = fp8x_splits(PP, h->n_pad, M);
+  const int S = fp8x_splits(PP, n_pad, M);
   if (h->f8_cap < (size_t)Mpad) {
     dfree(h, h->f8_Bq);
     dfree(h, h->f8_Bs);
@@ -992,16 +993,20 @@ static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, i
   a.moff = h->f8_moff;
   a.yb = h->f8_yb;
   a.n = h->n;
-  a.n_pad = h->n_pad;
+  a.n_pad = n_pad;
   a.M = M;
   a.M_pad = Mpad;
   a.S = S;
   a.spl_part = h->f8_part;
   a.ll = out;
   tbeg(h, SPA_T_LOGLIK);
-  const hipError_t e = launch_fp8x_loglik(a, h->stream);
+  SPA_CK(h, launch_fp8x_loglik(a, h->stream));
   tend(h);
-  SPA_CK(h, e);
+  if (S > 1) {
+    tbeg(h, SPA_T_FINALIZE);
+    SPA_CK(h, launch_fp8x_finalize(a, h->stream));
+    tend(h);
+  }
   return SPA_OK;
 }
 

@@ -7,6 +7,8 @@
 
 namespace spa {
 
+// Individuals per tile of the contraction; the genotype copy pads individuals to a multiple.
+constexpr int kF8Tile = 128;
 // Markers padded to whole 128-wide K steps of the FP8 MFMA: 128, 256, 384 or 512 (-1: p too large).
 int fp8x_pad_markers(int p);
 // Particles per workgroup (operand rows are padded to it; divides 128).
@@ -15,7 +17,7 @@ int fp8x_particles_per_wg(int PP);
 struct Fp8xArgs {
   int nterm;            // 3 or 4 coefficient terms
   int PP;               // padded markers (fp8x_pad_markers)
-  const uint8_t *Xf;    // n_pad x PP genotype codes (e4m3), zero padded
+  const uint8_t *Xf;    // n_pad x PP genotype codes (e4m3), zero padded; n_pad % kF8Tile == 0
   const uint8_t *Bq;    // nterm x M_pad x PP e4m3 codes of the coefficient terms
   const int32_t *Bs;    // nterm x M_pad biased exponents (E8M0) of the terms' scales
   const double *moff;   // M_pad: log2(e) sum_j mu_j b_ij of the represented coefficients
@@ -35,7 +37,9 @@ hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, i
                               uint8_t *Bq, int32_t *Bs, double *moff, double *yb, hipStream_t st);
 // Splits for a launch over M particles (same policy as the BF16 contraction).
 int fp8x_splits(int PP, int n_pad, int M);
-// The contraction, then (S > 1) the ordered combination of the split partials.
+// The contraction; with S > 1 it leaves split partials that launch_fp8x_finalize adds in
+// split order into ll (a no-op for S = 1).
 hipError_t launch_fp8x_loglik(const Fp8xArgs &a, hipStream_t st);
+hipError_t launch_fp8x_finalize(const Fp8xArgs &a, hipStream_t st);
 
 }  // namespace spa
