@@ -44,6 +44,7 @@ def test_fp8x_loglik_parity(name, M):
             print(f"{name} {prec} {dt}: max rel {errs[prec, dt]:.3e}")
         assert errs["fp8x3", dt] <= 1e-4
         assert errs["fp8x4", dt] <= 1e-4
+        assert errs["fp8x4", dt] <= errs["bf16x2", dt]
     s.close()
 
 
