@@ -54,33 +54,8 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 constexpr double kLog2eF8 = 1.44269504088896340736;
 constexpr int kF8Unit = 127;   // E8M0 code of 2^0
 
-// ---------------------------------------------------------------- e4m3 (OCP) encode / decode
-// Round-to-nearest-even onto the normal e4m3 values and zero; |x| >= 448 saturates to 448
-// (not reached: every scaled residual is below 256).
-__device__ __forceinline__ uint32_t e4m3_encode_normal(double x) {
-  const uint32_t sgn = x < 0.0 ? 0x80u : 0u;
-  const double a = fabs(x);
-  if (!(a >= 0x1p-7)) return sgn;          // zero (and NaN, which the caller flags)
-  if (a < 0x1p-6) return sgn | 0x08u;      // nearest normal is the smallest one
-  if (a >= 448.0) return sgn | 0x7Eu;
-  int k;
-  frexp(a, &k);
-  int e = k - 1;                            // a in [2^e, 2^(e+1))
-  int m = static_cast<int>(rint(ldexp(a, 3 - e)));   // 8..16
-  if (m == 16) {
-    m = 8;
-    ++e;
-  }
-  return sgn | static_cast<uint32_t>(((e + 7) << 3) | (m - 8));
-}
-__device__ __forceinline__ double e4m3_decode(uint32_t c) {
-  const int e = (c >> 3) & 0xF, m = c & 7;
-  const double v = e == 0 ? ldexp(static_cast<double>(m), -9) : ldexp(static_cast<double>(8 + m), e - 10);
-  return (c & 0x80u) ? -v : v;
-}
-
-// Genotype code of an integer value 0..15 (all exact in e4m3).
-__device__ __forceinline__ uint8_t e4m3_of_int(int v) { return static_cast<uint8_t>(e4m3_encode_normal(v)); }
+// Genotype codes (validated 0, 1 or 2 at init) in OCP e4m3: 0, 1.0 = 0x38, 2.0 = 0x40.
+__device__ __forceinline__ uint8_t genotype_code(uint8_t v) { return v == 0 ? 0 : (v == 1 ? 0x38 : 0x40); }
 
 // ---------------------------------------------------------------- packing
 __global__ void fp8x_pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad, int PP,
@@ -89,7 +64,7 @@ __global__ void fp8x_pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, 
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int k = static_cast<int>(idx / PP), j = static_cast<int>(idx % PP);
-    Xf[idx] = (k < n && j < p) ? e4m3_of_int(X[(size_t)k * p + j]) : uint8_t(0);
+    Xf[idx] = (k < n && j < p) ? genotype_code(X[(size_t)k * p + j]) : uint8_t(0);
   }
 }
 
@@ -134,10 +109,12 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
     for (int u = 0; u < JM; ++u) {
       const int j = lane + 64 * u;
       if (j < PP) {
-        const double x = ldexp(v[u] - used[u], -E);
-        const uint32_t c = fabs(x) >= 1.0 ? e4m3_encode_normal(x) : 0u;
+        // scaled residual below 256 in magnitude; the hardware conversion rounds it to the
+        // nearest e4m3 value, and the decoded code (the value the MFMA uses) is what counts
+        const float x = static_cast<float>(ldexp(v[u] - used[u], -E));
+        const int c = fabsf(x) >= 1.0f ? (__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF) : 0;
         q[j] = static_cast<uint8_t>(c);
-        used[u] += ldexp(e4m3_decode(c), E);
+        used[u] += ldexp(static_cast<double>(__builtin_amdgcn_cvt_f32_fp8(c, 0)), E);
       }
     }
     if (lane == 0) Bs[(size_t)t * M_pad + i] = E + kF8Unit;

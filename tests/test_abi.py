@@ -35,6 +35,13 @@ def test_header_declares_the_path_entry_points():
     assert sorted(binding.EXPORTS) == names
 
 
+def test_binding_precision_names_match_the_header_enum():
+    src = open(HEADER).read()
+    enum = dict((m.group(1).lower(), int(m.group(2)))
+                for m in re.finditer(r"SPA_PREC_(\w+)\s*=\s*(\d+)", src))
+    assert enum == binding.PREC
+
+
 def test_library_exports_every_declared_symbol(lib):
     for name in declared_functions():
         assert hasattr(lib, name), name
@@ -76,6 +83,8 @@ CASES = [
     ("ess_frac > 1", dict(ess_frac=1.5), binding.SPA_ERR_ARG),
     ("bad move", dict(move=7), binding.SPA_ERR_ARG),
     ("bad prec", dict(prec=9), binding.SPA_ERR_ARG),
+    ("FP8 3-term prec is for loglik calls only", dict(prec=3), binding.SPA_ERR_ARG),
+    ("FP8 4-term prec is for loglik calls only", dict(prec=4), binding.SPA_ERR_ARG),
     ("negative sweeps", dict(sweeps=-1), binding.SPA_ERR_ARG),
     ("step0 = 0", dict(step0=0.0), binding.SPA_ERR_ARG),
 ]
