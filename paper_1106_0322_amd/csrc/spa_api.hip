@@ -112,9 +112,8 @@ struct spa_smc {
   double *llscr = nullptr;
   size_t llscr_cap = 0;
   // FP8 multi-term forward contraction (loglik calls only)
-  uint8_t *f8_X = nullptr;       // (n rounded up to kF8Tile) x f8_PP genotype codes
-  int f8_PP = 0;
-  uint8_t *f8_Bq = nullptr;      // 4 x f8_cap x f8_PP term codes
+  uint8_t *f8_X = nullptr;       // (n rounded up to kF8Tile) x PP8 genotype codes, PP8 = fp8x_pad_markers(p)
+  uint8_t *f8_Bq = nullptr;      // 4 x f8_cap x PP8 term codes
   int32_t *f8_Bs = nullptr;      // 4 x f8_cap term exponents
   double *f8_moff = nullptr, *f8_yb = nullptr, *f8_part = nullptr;
   size_t f8_cap = 0;             // particle rows of the buffers above
@@ -961,7 +960,6 @@ static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, i
   if (!h->f8_X) {
     if ((st = dalloc(h, &h->f8_X, (size_t)n_pad * PP)) != SPA_OK) return st;
     SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
-    h->f8_PP = PP;
   }
   const int Mpad = round_up(M, kPartPad);
   const int S = fp8x_splits(PP, n_pad, M);

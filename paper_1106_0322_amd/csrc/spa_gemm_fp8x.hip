@@ -44,6 +44,7 @@
 // byte 0 of a per-lane register; every lane of a column carries the same exponent.
 #include "spa_common.hpp"
 #include "spa_gemm_fp8x.hpp"
+#include "spa_internal.hpp"
 
 namespace spa {
 
@@ -51,7 +52,6 @@ namespace {
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 
-constexpr double kLog2eF8 = 1.44269504088896340736;
 constexpr int kF8Unit = 127;   // E8M0 code of 2^0
 
 // Genotype codes (validated 0, 1 or 2 at init) in OCP e4m3: 0, 1.0 = 0x38, 2.0 = 0x40.
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
 #pragma unroll
   for (int u = 0; u < JM; ++u) {
     const int j = lane + 64 * u;
-    v[u] = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * inv_s[j] * kLog2eF8 : 0.0;
+    v[u] = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * inv_s[j] * kLog2e : 0.0;
     used[u] = 0.0;
     bad |= !isfinite(v[u]);
   }
@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
   if (lane == 0) {
     const double nan = __builtin_nan("");
     moff[i] = bad ? nan : m;
-    yb[i] = bad ? nan : ybv / kLog2eF8;
+    yb[i] = bad ? nan : ybv / kLog2e;
   }
 }
 
