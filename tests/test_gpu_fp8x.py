@@ -68,13 +68,14 @@ def test_fp8x_loglik_edge_shapes(n, p, M, prec):
     s.close()
 
 
-def test_fp8x_full_size_sampled():
-    """At 16384 particles on the 5000 x 200 data set (the launch shape of the timed
-    comparison), sampled particles against the oracle one by one."""
+@pytest.mark.parametrize("name,M", [("n5000_p200_mala_bf16", 16384), ("n10000_p500_mala_fp8", 32768)])
+def test_fp8x_full_size_sampled(name, M):
+    """At the particle counts of the timed comparison on the 5000 x 200 and 10000 x 500
+    data sets (two individual splits each; 256 and 512 padded markers), sampled particles
+    against the oracle one by one."""
     torch = _torch()
-    s, cfg, X, y, Xs = _sampler("n5000_p200_mala_bf16")
-    M = 16384
-    b = particles(M, X.shape[1], seed=7)
+    s, cfg, X, y, Xs = _sampler(name)
+    b = particles(M, X.shape[1], seed=7, scale=0.15 if X.shape[1] <= 256 else 0.06)
     bt = torch.from_numpy(b).to("cuda", torch.float32)
     idx = np.random.default_rng(1).choice(M, size=256, replace=False)
     ref = likelihood.loglik(bt.double().cpu().numpy()[idx], Xs, y)
@@ -82,7 +83,7 @@ def test_fp8x_full_size_sampled():
         got = s.loglik(bt, prec).cpu().numpy()
         assert np.all(np.isfinite(got))
         e = rel_err(got[idx], ref)
-        print(f"{prec} M={M}: sampled max rel {e.max():.3e}")
+        print(f"{name} {prec} M={M}: sampled max rel {e.max():.3e}")
         assert e.max() <= 1e-4
     s.close()
 
