@@ -961,8 +961,8 @@ static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, i
     if ((st = dalloc(h, &h->f8_X, (size_t)n_pad * PP)) != SPA_OK) return st;
     SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
   }
-  const int Mpad = round_up(M, kPartPad);
-  const int S = fp8x_splits(PP, n_pad, M);
+  const int Mpad = round_up(M, std::max(kPartPad, fp8x_particles_per_wg(PP, nterm)));
+  const int S = fp8x_splits(PP, nterm, n_pad, M);
   if (h->f8_cap < (size_t)Mpad) {
     dfree(h, h->f8_Bq);
     dfree(h, h->f8_Bs);

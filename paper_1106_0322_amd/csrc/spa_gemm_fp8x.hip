@@ -138,10 +138,15 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
 }
 
 // ---------------------------------------------------------------- contraction
-template <int PP>
+// Waves per workgroup: with rows of up to 256 markers, 3 terms fit 4 waves per SIMD
+// (120 VGPRs; measured 63 -> 59 us at 5000 individuals, 200 markers, 16384 particles),
+// 4 terms 2 (at 4 they spill); wider rows 1.
+__host__ __device__ constexpr int f8_waves(int PP, int nterm) { return PP <= 256 ? (nterm == 3 ? 16 : 8) : 4; }
+
+template <int PP, int NTERM>
 struct F8Shape {
   static constexpr int NT = kF8Tile;                // individuals per tile
-  static constexpr int NW = PP <= 256 ? 8 : 4;      // waves per workgroup (2 or 1 per SIMD)
+  static constexpr int NW = f8_waves(PP, NTERM);
   static constexpr int NTHR = 64 * NW;
   static constexpr int WGP = 16 * NW;               // particles per workgroup
   static constexpr int CPR = PP / 16, CX = CPR + 1; // 16-byte chunks per row; odd LDS stride
@@ -154,9 +159,9 @@ __device__ __forceinline__ void f8_lds_dma16(const void *g, uint4 *lds) {
 }
 
 template <int PP, int NTERM>
-__global__ __attribute__((amdgpu_flat_work_group_size(64, (F8Shape<PP>::NTHR))))
-__attribute__((amdgpu_waves_per_eu((F8Shape<PP>::NW / 4), (F8Shape<PP>::NW / 4)))) void fp8x_loglik_kernel(Fp8xArgs args) {
-  using SH = F8Shape<PP>;
+__global__ __attribute__((amdgpu_flat_work_group_size(64, (F8Shape<PP, NTERM>::NTHR))))
+__attribute__((amdgpu_waves_per_eu((F8Shape<PP, NTERM>::NW / 4), (F8Shape<PP, NTERM>::NW / 4)))) void fp8x_loglik_kernel(Fp8xArgs args) {
+  using SH = F8Shape<PP, NTERM>;
   constexpr int NT = SH::NT, IB = NT / 16, NKS = PP / 128, CX = SH::CX, CPR = SH::CPR;
   constexpr int XSL = SH::XSL, NTHR = SH::NTHR, WGP = SH::WGP, NQ = XSL / NTHR;
   extern __shared__ __align__(16) uint4 smem[];
@@ -215,41 +220,46 @@ __attribute__((amdgpu_waves_per_eu((F8Shape<PP>::NW / 4), (F8Shape<PP>::NW / 4))
     // next tile (the last one re-copies itself into the idle stage, never read)
     issue(i0 + min(it + 1, ntiles - 1) * NT, stage ^ 1);
     const uint4 *sX = smem + stage * XSL;
-    f32x4 acc[IB];
+    // the tile in quarters of HB 16-individual blocks (bounds the fragment registers)
+    constexpr int HB = 4;
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib) acc[ib] = f32x4{0, 0, 0, 0};
+    for (int h = 0; h < IB / HB; ++h) {
+      f32x4 acc[HB];
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      i32x8 a[IB];
+      for (int ib = 0; ib < HB; ++ib) acc[ib] = f32x4{0, 0, 0, 0};
 #pragma unroll
-      for (int ib = 0; ib < IB; ++ib) {
-        const uint4 *rp = sX + (ib * 16 + lr) * CX + ks * 8 + lg;
-        const uint4 lo = rp[0], hi = rp[4];
-        a[ib] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
-      }
+      for (int ks = 0; ks < NKS; ++ks) {
+        i32x8 a[HB];
 #pragma unroll
-      for (int t = 0; t < NTERM; ++t)
-#pragma unroll
-        for (int ib = 0; ib < IB; ++ib)
-          acc[ib] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[ib], b[t][ks], acc[ib], 0, 0, 0,
-                                                                     0x7F7F7F7F, 0, sc[t]);
-    }
-    // softplus sum of the tile, in base 2 (the operand carries log2(e)): lane holds particle
-    // lr and individuals 16 ib + 4 lg + v; one log per tile of the product of <= 32 factors
-    // in (1, 2] (below 2^32: no overflow in FP32).
-    float prod = 1.0f, mx = 0.0f;
-#pragma unroll
-    for (int ib = 0; ib < IB; ++ib)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const float z = acc[ib][v] - moff;
-        const float e = __builtin_amdgcn_exp2f(-fabsf(z));
-        if (!MASKED || tile0 + ib * 16 + 4 * lg + v < n) {
-          prod = fmaf(prod, e, prod);
-          mx += fmaxf(z, 0.0f);
+        for (int ib = 0; ib < HB; ++ib) {
+          const uint4 *rp = sX + ((h * HB + ib) * 16 + lr) * CX + ks * 8 + lg;
+          const uint4 lo = rp[0], hi = rp[4];
+          a[ib] = i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w, (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
         }
+#pragma unroll
+        for (int t = 0; t < NTERM; ++t)
+#pragma unroll
+          for (int ib = 0; ib < HB; ++ib)
+            acc[ib] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[ib], b[t][ks], acc[ib], 0, 0, 0,
+                                                                       0x7F7F7F7F, 0, sc[t]);
       }
-    spl += static_cast<double>(0.6931471805599453f * (mx + __builtin_amdgcn_logf(prod)));
+      // softplus sum, in base 2 (the operand carries log2(e)): lane holds particle lr and
+      // individuals 16 (h HB + ib) + 4 lg + v; one log of the product of <= 16 factors in
+      // (1, 2].
+      float prod = 1.0f, mx = 0.0f;
+#pragma unroll
+      for (int ib = 0; ib < HB; ++ib)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const float z = acc[ib][v] - moff;
+          const float e = __builtin_amdgcn_exp2f(-fabsf(z));
+          if (!MASKED || tile0 + (h * HB + ib) * 16 + 4 * lg + v < n) {
+            prod = fmaf(prod, e, prod);
+            mx += fmaxf(z, 0.0f);
+          }
+        }
+      spl += static_cast<double>(0.6931471805599453f * (mx + __builtin_amdgcn_logf(prod)));
+    }
     land();
   };
   const bool has_tail = ntiles > 0 && i0 + ntiles * NT > n;
@@ -278,7 +288,7 @@ __global__ void fp8x_finalize_kernel(Fp8xArgs args) {
 
 template <int PP, int NTERM>
 hipError_t launch_fp8x_one(const Fp8xArgs &a, hipStream_t st) {
-  constexpr size_t lds = F8Shape<PP>::bytes;
+  constexpr size_t lds = F8Shape<PP, NTERM>::bytes;
   static_assert(lds <= 160 * 1024, "LDS budget of one CU");
   auto kern = fp8x_loglik_kernel<PP, NTERM>;
   static bool attr_set = false;
@@ -288,11 +298,11 @@ hipError_t launch_fp8x_one(const Fp8xArgs &a, hipStream_t st) {
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  constexpr int per_wg = F8Shape<PP>::WGP;
+  constexpr int per_wg = F8Shape<PP, NTERM>::WGP;
   const int tiles_p = (a.M + per_wg - 1) / per_wg;
   const int g8 = 8 / a.S;
   const int grid = 8 * ((tiles_p + g8 - 1) / g8);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(F8Shape<PP>::NTHR), lds, st, a);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(F8Shape<PP, NTERM>::NTHR), lds, st, a);
   return hipGetLastError();
 }
 
@@ -314,10 +324,10 @@ int fp8x_pad_markers(int p) {
   return (p >= 1 && PP <= 512) ? PP : -1;
 }
 
-int fp8x_particles_per_wg(int PP) { return 16 * (PP <= 256 ? 8 : 4); }
+int fp8x_particles_per_wg(int PP, int nterm) { return 16 * f8_waves(PP, nterm); }
 
-int fp8x_splits(int PP, int n_pad, int M) {
-  const int NT = kF8Tile, per_wg = fp8x_particles_per_wg(PP);
+int fp8x_splits(int PP, int nterm, int n_pad, int M) {
+  const int NT = kF8Tile, per_wg = fp8x_particles_per_wg(PP, nterm);
   const int tiles_p = (M + per_wg - 1) / per_wg;
   const size_t x_bytes = (size_t)n_pad * PP;
   int S = 1;
@@ -356,7 +366,7 @@ hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, i
 
 hipError_t launch_fp8x_loglik(const Fp8xArgs &a, hipStream_t st) {
   if (a.S != 1 && a.S != 2 && a.S != 4 && a.S != 8) return hipErrorInvalidValue;
-  if (a.M_pad % fp8x_particles_per_wg(a.PP) != 0 || a.n_pad % kF8Tile != 0) return hipErrorInvalidValue;
+  if (a.M_pad % fp8x_particles_per_wg(a.PP, a.nterm) != 0 || a.n_pad % kF8Tile != 0) return hipErrorInvalidValue;
   return a.nterm == 3 ? launch_fp8x_terms<3>(a, st)
          : a.nterm == 4 ? launch_fp8x_terms<4>(a, st) : hipErrorInvalidValue;
 }

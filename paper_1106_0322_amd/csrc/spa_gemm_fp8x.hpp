@@ -11,8 +11,8 @@ namespace spa {
 constexpr int kF8Tile = 128;
 // Markers padded to whole 128-wide K steps of the FP8 MFMA: 128, 256, 384 or 512 (-1: p too large).
 int fp8x_pad_markers(int p);
-// Particles per workgroup (operand rows are padded to it; divides 128).
-int fp8x_particles_per_wg(int PP);
+// Particles per workgroup for nterm terms (64, 128 or 256; operand rows are padded to it).
+int fp8x_particles_per_wg(int PP, int nterm);
 
 struct Fp8xArgs {
   int nterm;            // 3 or 4 coefficient terms
@@ -36,7 +36,7 @@ hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, i
                               const double *mu, const double *s, const double *inv_s, const double *ytil,
                               uint8_t *Bq, int32_t *Bs, double *moff, double *yb, hipStream_t st);
 // Splits for a launch over M particles (same policy as the BF16 contraction).
-int fp8x_splits(int PP, int n_pad, int M);
+int fp8x_splits(int PP, int nterm, int n_pad, int M);
 // The contraction; with S > 1 it leaves split partials that launch_fp8x_finalize adds in
 // split order into ll (a no-op for S = 1).
 hipError_t launch_fp8x_loglik(const Fp8xArgs &a, hipStream_t st);
