@@ -140,8 +140,8 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
 // ---------------------------------------------------------------- contraction
 // Waves per workgroup: with rows of up to 256 markers, 3 terms fit 4 waves per SIMD
 // (120 VGPRs; measured 63 -> 59 us at 5000 individuals, 200 markers, 16384 particles),
-// 4 terms 2 (at 4 they spill); wider rows 1.
-__host__ __device__ constexpr int f8_waves(int PP, int nterm) { return PP <= 256 ? (nterm == 3 ? 16 : 8) : 4; }
+// 4 terms 2 (at 4 they spill); wider rows 2 (at most 210 VGPRs).
+__host__ __device__ constexpr int f8_waves(int PP, int nterm) { return PP <= 256 ? (nterm == 3 ? 16 : 8) : 8; }
 
 template <int PP, int NTERM>
 struct F8Shape {
