@@ -280,6 +280,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="n5000_p200_mala_bf16")
     ap.add_argument("--init-sweeps", type=int, default=None)
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16x2", "fp8x3", "fp8x4"],
+                    help="override the workload's contraction precision (fp8x*: random-walk moves)")
+    ap.add_argument("--move", default=None, choices=["rwm", "mala"], help="override the workload's move")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the ESS/s protocol")
     ap.add_argument("--ess-seeds", type=int, default=8)
@@ -303,6 +306,11 @@ def main():
     from synth import CONFIGS, make_dataset
 
     cfg = CONFIGS[args.workload]
+    # the committed counter summaries describe the workload as configured
+    prof_key = args.workload
+    if args.prec is not None or args.move is not None:
+        cfg = cfg.replace(prec=args.prec or cfg.prec, move=args.move or cfg.move)
+        prof_key = None
     if args.steps + args.warmup + BREAKDOWN_STEPS > cfg.T - 1:
         sys.exit(f"steps + warmup must be <= {cfg.T - 1 - BREAKDOWN_STEPS} scales")
     d = make_dataset(cfg)
@@ -335,10 +343,10 @@ def main():
     achieved = gemm_flops(cfg) / (gemm_avg_ms * 1e-3) / 1e12
     # executed matrix work (hi and lo products over the padded shapes) from the committed
     # counter summary, over this run's live launch time; and the counters' pipe-busy share
-    mf = profile_values(MFMA_PROFILE, args.workload)
+    mf = profile_values(MFMA_PROFILE, prof_key)
     executed = None if mf is None else float(mf["mfma_flops_per_launch"]) / (gemm_avg_ms * 1e-3) / 1e12
-    dtype = {"bf16x2": "bf16", "fp32": "f32", "fp64": "f64"}[cfg.prec]
-    peak = PEAK[cfg.prec]
+    dtype = {"bf16x2": "bf16", "fp32": "f32", "fp64": "f64", "fp8x3": "fp8", "fp8x4": "fp8"}[cfg.prec]
+    peak = PEAK_FP8 if cfg.prec.startswith("fp8x") else PEAK[cfg.prec]
     out = {
         "metric": "loglik TFLOP/s + SPA sweep ESS/sec: plain FP32 RWM vs mixed-prec MALA",
         "value": round(value, 3),
@@ -359,9 +367,10 @@ def main():
                    "move": cfg.move, "prec": cfg.prec},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
-                     "traffic": profiled_traffic(args.workload),
+                     "traffic": profiled_traffic(prof_key),
                      "kernel": "loglik_kernel (fused log-likelihood + adjoint)" if cfg.move == "mala"
-                     else "loglik_kernel", "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
+                     else ("fp8x_loglik_kernel" if cfg.prec.startswith("fp8x") else "loglik_kernel"),
+                     "avg_launch_us": round(gemm_avg_ms * 1e3, 2),
                      "executed_TFLOPs": None if executed is None else round(executed, 2),
                      "executed_frac": None if executed is None else round(executed / peak, 4),
                      "mfma_busy_frac": None if mf is None else float(mf["mfma_busy_frac"])},

@@ -57,10 +57,10 @@ typedef enum {
   SPA_PREC_BF16X2 = 2,  /* genotypes exact in BF16 (or FP8 storage), beta/s split into BF16
                            hi + lo parts, residuals likewise, FP32 MFMA accumulation:
                            per-particle loglik rel. err < 1e-4                             */
-  SPA_PREC_FP8X3 = 3,   /* forward log-likelihood only (spa_smc_loglik): genotypes exact in
-                           e4m3, beta/s split into 3 e4m3 terms with per-particle power-of-
-                           two scales (the block scales of the FP8 MFMA), FP32 accumulation:
-                           per-particle loglik rel. err < 1e-4; p <= 512                   */
+  SPA_PREC_FP8X3 = 3,   /* forward log-likelihood only (spa_smc_loglik, random-walk sweeps):
+                           genotypes exact in e4m3, beta/s split into 3 e4m3 terms with
+                           per-particle power-of-two scales (the block scales of the FP8
+                           MFMA), FP32 accumulation: per-particle loglik rel. err < 1e-4   */
   SPA_PREC_FP8X4 = 4    /* as SPA_PREC_FP8X3 with 4 terms: rel. err below the BF16X2 one    */
 } spa_prec;
 
@@ -85,8 +85,8 @@ typedef struct {
   double step0;           /* initial random-walk kappa or MALA h, > 0                    */
   int32_t adapt;          /* 1: log step += clip(acceptance - target, -log 2, log 2) after
                              each burn-in sweep and each scale; 0: fixed step            */
-  spa_prec prec;          /* GEMM precision of the moves (FP64, FP32 or BF16X2; the FP8
-                             multi-term ones are for spa_smc_loglik only); particles are
+  spa_prec prec;          /* GEMM precision of the moves (the FP8 multi-term ones with
+                             SPA_MOVE_RWM only: they have no adjoint); particles are
                              stored in FP64 for SPA_PREC_FP64 and in FP32 otherwise       */
   spa_xfmt xfmt;          /* genotype storage for SPA_PREC_BF16X2                         */
   uint64_t seed;          /* Philox4x32-10 key (low word, high word)                      */
@@ -136,8 +136,9 @@ spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out);
  * spa_smc_loglik -- log f(y | X, beta_i) for M particles (Section 2 likelihood):
  * sum_k [y_k eta_ik - log(1 + exp(eta_ik))], eta_i = X_std beta_i.
  * beta_dev: M x p, FP64 if beta_is_fp64 else FP32.  loglik_dev: M doubles (output).
- * prec selects the contraction precision; the FP8 multi-term precisions (SPA_PREC_FP8X3,
- * SPA_PREC_FP8X4) are served here only: the coefficient row of each particle is written as
+ * prec selects the contraction precision.  With the FP8 multi-term precisions
+ * (SPA_PREC_FP8X3, SPA_PREC_FP8X4; the random-walk sweeps of a handle created with one of
+ * them pack their proposals the same way) the coefficient row of each particle is written as
  * sum_t 2^E_t q_t with e4m3 entries q_t, term t taking the residual of the terms before it
  * scaled so that its largest entry lies in [128, 256) (Section 2 likelihood on the
  * represented coefficients, whose offsets and X_std^T y term are formed exactly in FP64).
@@ -304,7 +305,8 @@ spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uin
  */
 enum {
   SPA_T_PROPOSE = 0,    /* proposal + scaled-coefficient operand (first sweep of a   */
-                        /* step; burn-in sweeps; single-coordinate cycles)             */
+                        /* step; burn-in sweeps; single-coordinate cycles; with the    */
+                        /* FP8 precisions, every sweep's packing into e4m3 terms)      */
   SPA_T_LOGLIK = 1,     /* MFMA log-likelihood contraction (+ adjoint for MALA)        */
   SPA_T_ACCEPT = 2,     /* Metropolis-Hastings decisions; within a step, every sweep */
                         /* but the last also draws the next sweep's proposal here      */

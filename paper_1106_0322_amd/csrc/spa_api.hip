@@ -111,7 +111,9 @@ struct spa_smc {
   size_t g_part_cap = 0;
   double *llscr = nullptr;
   size_t llscr_cap = 0;
-  // FP8 multi-term forward contraction (loglik calls only)
+  // FP8 multi-term forward contraction (loglik calls, and the contraction of random-walk
+  // sweeps when the handle's precision is one of the FP8 ones)
+  int f8_terms = 0;              // 3 or 4 when the sampler contracts on the FP8 MFMA
   uint8_t *f8_X = nullptr;       // (n rounded up to kF8Tile) x PP8 genotype codes, PP8 = fp8x_pad_markers(p)
   uint8_t *f8_Bq = nullptr;      // 4 x f8_cap x PP8 term codes
   int32_t *f8_Bs = nullptr;      // 4 x f8_cap term exponents
@@ -364,8 +366,73 @@ spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad,
   return SPA_OK;
 }
 
+// Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
+// With finalize = false and more than one individual split the partial sums are left for
+// the caller (the MH decision combines them), and *used describes them.
+// time_pack: bracket the packing as the proposal class (the sampler's sweeps).
+spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out,
+                         bool finalize, Fp8xArgs *used, bool time_pack = false) {
+  spa_status st;
+  const int PP = fp8x_pad_markers(h->p);
+  if (PP < 0) return set_err(h, SPA_ERR_ARG, "FP8 multi-term path needs p <= 512");
+  const int n_pad = round_up(h->n, kF8Tile);
+  if (!h->f8_X) {
+    if ((st = dalloc(h, &h->f8_X, (size_t)n_pad * PP)) != SPA_OK) return st;
+    SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
+  }
+  const int Mpad = round_up(M, std::max(kPartPad, fp8x_particles_per_wg(PP, nterm)));
+  const int S = fp8x_splits(PP, nterm, n_pad, M);
+  if (h->f8_cap < (size_t)Mpad) {
+    dfree(h, h->f8_Bq);
+    dfree(h, h->f8_Bs);
+    dfree(h, h->f8_moff);
+    dfree(h, h->f8_yb);
+    dfree(h, h->f8_part);
+    h->f8_Bq = nullptr;
+    h->f8_Bs = nullptr;
+    h->f8_moff = h->f8_yb = h->f8_part = nullptr;
+    h->f8_cap = 0;
+    if ((st = dalloc(h, &h->f8_Bq, 4 * (size_t)Mpad * PP)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_Bs, 4 * 4 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_moff, 8 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_yb, 8 * (size_t)Mpad)) != SPA_OK) return st;
+    if ((st = dalloc(h, &h->f8_part, 8 * 8 * (size_t)Mpad)) != SPA_OK) return st;
+    h->f8_cap = Mpad;
+  }
+  if (time_pack) tbeg(h, SPA_T_PROPOSE);
+  SPA_CK(h, launch_fp8x_pack_b(nterm, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil,
+                               h->f8_Bq, h->f8_Bs, h->f8_moff, h->f8_yb, h->stream));
+  if (time_pack) tend(h);
+  Fp8xArgs a{};
+  a.nterm = nterm;
+  a.PP = PP;
+  a.Xf = h->f8_X;
+  a.Bq = h->f8_Bq;
+  a.Bs = h->f8_Bs;
+  a.moff = h->f8_moff;
+  a.yb = h->f8_yb;
+  a.n = h->n;
+  a.n_pad = n_pad;
+  a.M = M;
+  a.M_pad = Mpad;
+  a.S = S;
+  a.spl_part = h->f8_part;
+  a.ll = out;
+  tbeg(h, SPA_T_LOGLIK);
+  SPA_CK(h, launch_fp8x_loglik(a, h->stream));
+  tend(h);
+  if (S > 1 && finalize) {
+    tbeg(h, SPA_T_FINALIZE);
+    SPA_CK(h, launch_fp8x_finalize(a, h->stream));
+    tend(h);
+  }
+  if (used) *used = a;
+  return SPA_OK;
+}
+
 // Log-likelihood (and gradient) of the handle's own particle buffer `beta` into ll/g.
 spa_status eval_state(spa_smc *h, const void *beta, double *ll, void *g) {
+  if (h->f8_terms) return fp8x_contract(h, beta, h->N, 0, h->f8_terms, ll, true, nullptr);
   launch_pack_b(h->prec, h->f64, beta, h->N, h->Npad, h->p, h->PP, h->mu, h->s, h->inv_s, h->ytil,
                 h->op.Bhi, h->op.Blo, h->op.moff, h->op.yb, h->stream);
   const bool grad = h->move == SPA_MOVE_MALA;
@@ -411,11 +478,24 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
     launch_propose(h->prec, mala, pa, h->stream);
     tend(h);
   }
-  GemmArgs ga;
-  spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr, false, &ga);
-  if (st != SPA_OK) return st;
   AcceptArgs aa{};
-  if (ga.S > 1) {   // the MH decision combines the contraction's partial sums itself
+  if (h->f8_terms) {   // random-walk moves on the FP8 MFMA: the proposal is packed into terms
+    Fp8xArgs fa;
+    spa_status st = fp8x_contract(h, h->prop, h->N, 0, h->f8_terms, h->llp, false, &fa, true);
+    if (st != SPA_OK) return st;
+    if (fa.S > 1) {
+      aa.spl_part = fa.spl_part;
+      aa.S = fa.S;
+      aa.Mp = static_cast<size_t>(fa.M_pad);
+      aa.yb = fa.yb;
+    }
+  }
+  GemmArgs ga{};
+  if (!h->f8_terms) {
+    spa_status st = run_gemm(h, h->prec, h->op, h->N, mala, h->llp, mala ? h->glp : nullptr, false, &ga);
+    if (st != SPA_OK) return st;
+  }
+  if (!h->f8_terms && ga.S > 1) {   // the MH decision combines the contraction's partial sums itself
     aa.spl_part = ga.spl_part;
     aa.g_part = ga.g_part;
     aa.S = ga.S;
@@ -679,8 +759,11 @@ spa_status validate_cfg(const spa_smc_config *c) {
   if (!(c->ess_frac > 0.0 && c->ess_frac <= 1.0)) return set_err(nullptr, SPA_ERR_ARG, "ess_frac in (0, 1]");
   if (!(c->step0 > 0.0) || !std::isfinite(c->step0)) return set_err(nullptr, SPA_ERR_ARG, "step0 must be > 0");
   if (c->adapt != 0 && c->adapt != 1) return set_err(nullptr, SPA_ERR_ARG, "adapt must be 0 or 1");
-  if (c->prec != SPA_PREC_FP64 && c->prec != SPA_PREC_FP32 && c->prec != SPA_PREC_BF16X2)
+  const bool f8 = c->prec == SPA_PREC_FP8X3 || c->prec == SPA_PREC_FP8X4;
+  if (c->prec != SPA_PREC_FP64 && c->prec != SPA_PREC_FP32 && c->prec != SPA_PREC_BF16X2 && !f8)
     return set_err(nullptr, SPA_ERR_ARG, "bad prec");
+  if (f8 && c->move != SPA_MOVE_RWM)
+    return set_err(nullptr, SPA_ERR_ARG, "the FP8 multi-term contraction has no adjoint: random-walk moves only");
   if (c->xfmt != SPA_X_AUTO && c->xfmt != SPA_X_FP8E4M3 && c->xfmt != SPA_X_BF16)
     return set_err(nullptr, SPA_ERR_ARG, "bad xfmt");
   if (c->prec == SPA_PREC_FP64 && c->p > 255) return set_err(nullptr, SPA_ERR_SHAPE, "FP64 path needs p <= 255");
@@ -727,7 +810,8 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   h->ess_frac = cfg->ess_frac;
   h->step = cfg->step0;
   h->adapt = cfg->adapt;
-  h->prec = to_prec(cfg->prec);
+  h->prec = to_prec(cfg->prec);   // the FP8 precisions run the BF16 move kernels (FP32 particles)
+  h->f8_terms = cfg->prec == SPA_PREC_FP8X3 ? 3 : (cfg->prec == SPA_PREC_FP8X4 ? 4 : 0);
   h->xfmt = cfg->xfmt;
   h->k0 = static_cast<uint32_t>(cfg->seed & 0xFFFFFFFFull);
   h->k1 = static_cast<uint32_t>(cfg->seed >> 32);
@@ -951,69 +1035,13 @@ static spa_status prep_operand(spa_smc *h, const void *beta, int M, int is_f64, 
 
 static bool valid_prec(spa_prec p) { return p == SPA_PREC_FP64 || p == SPA_PREC_FP32 || p == SPA_PREC_BF16X2; }
 
-// Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
-static spa_status fp8x_loglik(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out) {
-  spa_status st;
-  const int PP = fp8x_pad_markers(h->p);
-  if (PP < 0) return set_err(h, SPA_ERR_ARG, "FP8 multi-term path needs p <= 512");
-  const int n_pad = round_up(h->n, kF8Tile);
-  if (!h->f8_X) {
-    if ((st = dalloc(h, &h->f8_X, (size_t)n_pad * PP)) != SPA_OK) return st;
-    SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
-  }
-  const int Mpad = round_up(M, std::max(kPartPad, fp8x_particles_per_wg(PP, nterm)));
-  const int S = fp8x_splits(PP, nterm, n_pad, M);
-  if (h->f8_cap < (size_t)Mpad) {
-    dfree(h, h->f8_Bq);
-    dfree(h, h->f8_Bs);
-    dfree(h, h->f8_moff);
-    dfree(h, h->f8_yb);
-    dfree(h, h->f8_part);
-    h->f8_Bq = nullptr;
-    h->f8_Bs = nullptr;
-    h->f8_moff = h->f8_yb = h->f8_part = nullptr;
-    h->f8_cap = 0;
-    if ((st = dalloc(h, &h->f8_Bq, 4 * (size_t)Mpad * PP)) != SPA_OK) return st;
-    if ((st = dalloc(h, &h->f8_Bs, 4 * 4 * (size_t)Mpad)) != SPA_OK) return st;
-    if ((st = dalloc(h, &h->f8_moff, 8 * (size_t)Mpad)) != SPA_OK) return st;
-    if ((st = dalloc(h, &h->f8_yb, 8 * (size_t)Mpad)) != SPA_OK) return st;
-    if ((st = dalloc(h, &h->f8_part, 8 * 8 * (size_t)Mpad)) != SPA_OK) return st;
-    h->f8_cap = Mpad;
-  }
-  SPA_CK(h, launch_fp8x_pack_b(nterm, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil,
-                               h->f8_Bq, h->f8_Bs, h->f8_moff, h->f8_yb, h->stream));
-  Fp8xArgs a{};
-  a.nterm = nterm;
-  a.PP = PP;
-  a.Xf = h->f8_X;
-  a.Bq = h->f8_Bq;
-  a.Bs = h->f8_Bs;
-  a.moff = h->f8_moff;
-  a.yb = h->f8_yb;
-  a.n = h->n;
-  a.n_pad = n_pad;
-  a.M = M;
-  a.M_pad = Mpad;
-  a.S = S;
-  a.spl_part = h->f8_part;
-  a.ll = out;
-  tbeg(h, SPA_T_LOGLIK);
-  SPA_CK(h, launch_fp8x_loglik(a, h->stream));
-  tend(h);
-  if (S > 1) {
-    tbeg(h, SPA_T_FINALIZE);
-    SPA_CK(h, launch_fp8x_finalize(a, h->stream));
-    tend(h);
-  }
-  return SPA_OK;
-}
 
 extern "C" spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
                                      spa_prec prec, double *loglik_dev) {
   if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
   if (!beta_dev || !loglik_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
   if (prec == SPA_PREC_FP8X3 || prec == SPA_PREC_FP8X4)
-    return fp8x_loglik(h, beta_dev, M, beta_is_fp64, prec == SPA_PREC_FP8X3 ? 3 : 4, loglik_dev);
+    return fp8x_contract(h, beta_dev, M, beta_is_fp64, prec == SPA_PREC_FP8X3 ? 3 : 4, loglik_dev, true, nullptr);
   if (!valid_prec(prec)) return set_err(h, SPA_ERR_ARG, "bad prec");
   if (prec == SPA_PREC_FP64 && h->p > 255) return set_err(h, SPA_ERR_ARG, "FP64 path needs p <= 255");
   const Prec P = to_prec(prec);

@@ -68,8 +68,8 @@ __global__ void fp8x_pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, 
   }
 }
 
-// One wave per particle row; up to 8 coefficients per lane (PP <= 512).
-template <int NTERM, typename IT>
+// One wave per particle row; JM = PP / 64 coefficients per lane.
+template <int NTERM, int JM, typename IT>
 __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int p,
                                                           int PP, const double *__restrict__ mu,
                                                           const double *__restrict__ s,
@@ -77,7 +77,6 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
                                                           const double *__restrict__ ytil, uint8_t *__restrict__ Bq,
                                                           int32_t *__restrict__ Bs, double *__restrict__ moff,
                                                           double *__restrict__ yb) {
-  constexpr int JM = 8;
   const int lane = threadIdx.x & 63;
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= M_pad) return;
@@ -350,16 +349,24 @@ hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, i
                               uint8_t *Bq, int32_t *Bs, double *moff, double *yb, hipStream_t st) {
   if (PP > 512 || PP % 128 != 0 || M_pad % 4 != 0) return hipErrorInvalidValue;
   const int grid = M_pad / 4;
-#define SPA_F8PACK(NT_, IT_)                                                                          \
-  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, IT_>), dim3(grid), dim3(256), 0, st, (const IT_ *)beta, M, \
+#define SPA_F8PACK(NT_, JM_, IT_)                                                                          \
+  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, JM_, IT_>), dim3(grid), dim3(256), 0, st, (const IT_ *)beta, M, \
                      M_pad, p, PP, mu, s, inv_s, ytil, Bq, Bs, moff, yb)
+#define SPA_F8PACK_JM(NT_, IT_)                 \
+  switch (PP) {                                 \
+    case 128: SPA_F8PACK(NT_, 2, IT_); break;   \
+    case 256: SPA_F8PACK(NT_, 4, IT_); break;   \
+    case 384: SPA_F8PACK(NT_, 6, IT_); break;   \
+    default: SPA_F8PACK(NT_, 8, IT_); break;    \
+  }
   if (nterm == 3) {
-    if (in_f64) SPA_F8PACK(3, double); else SPA_F8PACK(3, float);
+    if (in_f64) SPA_F8PACK_JM(3, double) else SPA_F8PACK_JM(3, float)
   } else if (nterm == 4) {
-    if (in_f64) SPA_F8PACK(4, double); else SPA_F8PACK(4, float);
+    if (in_f64) SPA_F8PACK_JM(4, double) else SPA_F8PACK_JM(4, float)
   } else {
     return hipErrorInvalidValue;
   }
+#undef SPA_F8PACK_JM
 #undef SPA_F8PACK
   return hipGetLastError();
 }

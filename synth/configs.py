@@ -32,7 +32,7 @@ class WorkloadConfig:
     move: str              # "rwm" or "mala"
     sweeps: int            # joint proposals per particle per scale
     init_sweeps: int       # burn-in sweeps targeting the first scale
-    prec: str              # GEMM precision: "fp64", "fp32" or "bf16x2"
+    prec: str              # GEMM precision: "fp64", "fp32", "bf16x2", or "fp8x3" / "fp8x4" (RWM)
     xfmt: str = "auto"     # genotype storage for bf16x2: "auto", "bf16" or "fp8"
     ess_frac: float = 0.5  # resample iff ESS < ess_frac * N
     seed: int = 0          # Philox key of the sampler

@@ -83,8 +83,8 @@ CASES = [
     ("ess_frac > 1", dict(ess_frac=1.5), binding.SPA_ERR_ARG),
     ("bad move", dict(move=7), binding.SPA_ERR_ARG),
     ("bad prec", dict(prec=9), binding.SPA_ERR_ARG),
-    ("FP8 3-term prec is for loglik calls only", dict(prec=3), binding.SPA_ERR_ARG),
-    ("FP8 4-term prec is for loglik calls only", dict(prec=4), binding.SPA_ERR_ARG),
+    ("FP8 3-term prec with MALA (no adjoint)", dict(prec=3, move=1), binding.SPA_ERR_ARG),
+    ("FP8 4-term prec with single-coordinate moves", dict(prec=4, move=2), binding.SPA_ERR_ARG),
     ("negative sweeps", dict(sweeps=-1), binding.SPA_ERR_ARG),
     ("step0 = 0", dict(step0=0.0), binding.SPA_ERR_ARG),
 ]

@@ -103,7 +103,7 @@ def test_fp8x_nonfinite_coefficient_gives_nan_for_that_particle_only():
     s.close()
 
 
-def test_fp8x_is_refused_by_the_sampler_and_the_gradient():
+def test_fp8x_is_refused_for_mala_and_the_gradient():
     from paper_1106_0322_amd import SamplerConfig, SpaSMC, SpaError
     torch = _torch()
     s, cfg, X, y, Xs = _sampler("n500_p10_rwm_fp64")
@@ -111,6 +111,33 @@ def test_fp8x_is_refused_by_the_sampler_and_the_gradient():
         s.grad(torch.zeros(4, X.shape[1], dtype=torch.float64, device="cuda"), 1.0, "fp8x4")
     s.close()
     sc = SamplerConfig(n=X.shape[0], p=X.shape[1], N=64, a=cfg.a, lambdas=np.geomspace(10, 1, 2),
-                       move="rwm", sweeps=0, init_sweeps=0, prec="fp8x3", seed=0)
+                       move="mala", sweeps=0, init_sweeps=0, prec="fp8x3", seed=0)
     with pytest.raises(SpaError):
         SpaSMC(sc, X, y)
+
+
+@pytest.mark.parametrize("prec", ["fp8x3", "fp8x4"])
+def test_fp8x_random_walk_sampler_full_size(prec):
+    """Random-walk sweeps contracting on the FP8 MFMA at the 5000 x 200, 16384-particle
+    shape: the log-likelihoods the sampler keeps are bit-identical to a fresh FP8
+    evaluation of its particles (same packing, same split order), and sampled rows are
+    within 1e-4 of the oracle."""
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    from synth import CONFIGS
+    torch = _torch()
+    cfg, X, y, Xs = dataset("n5000_p200_rwm_fp32")
+    w = cfg.replace(prec=prec)
+    s = SpaSMC(SamplerConfig.from_workload(w, n=X.shape[0], p=X.shape[1], init_sweeps=4), X, y)
+    out = s.step()
+    assert math.isfinite(out["ess"]) and 0.0 < out["accept_rate"] < 1.0
+    beta, logw = s.particles()
+    kept = s.state_loglik().cpu().numpy()
+    fresh = s.loglik(beta, prec).cpu().numpy()
+    assert np.array_equal(kept, fresh)
+    idx = np.random.default_rng(0).choice(w.N, size=48, replace=False)
+    ref = likelihood.loglik(beta[idx].double().cpu().numpy(), Xs, y)
+    e = rel_err(kept[idx], ref)
+    print(f"{prec} sampler: sampled loglik max rel err {e.max():.3e}, accept {out['accept_rate']:.3f}")
+    assert e.max() <= 1e-4
+    assert np.all(np.isfinite(logw.cpu().numpy()))
+    s.close()

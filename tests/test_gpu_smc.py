@@ -147,6 +147,7 @@ def stat_compare(gpu, orc):
 @pytest.mark.parametrize("name,over,Rg,Ro", [
     ("n2000_p50_rwm_fp32", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
     ("n2000_p50_rwm_fp8", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
+    ("n2000_p50_rwm_fp32", dict(N=1024, T=12, sweeps=5, init_sweeps=100, prec="fp8x3"), 8, 5),
     ("n5000_p200_mala_bf16", dict(N=1024, T=12, sweeps=5, init_sweeps=100), 8, 5),
 ])
 def test_statistical_parity(name, over, Rg, Ro):
