@@ -68,8 +68,29 @@ __global__ void fp8x_pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, 
   }
 }
 
-// One wave per particle row; JM = PP / 64 coefficients per lane.
-template <int NTERM, int JM, typename IT>
+// Reductions over the LN lanes of a particle (fixed xor-butterfly order).
+template <int LN>
+__device__ __forceinline__ double f8_group_max(double v) {
+#pragma unroll
+  for (int o = LN / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+template <int LN>
+__device__ __forceinline__ double f8_group_sum(double v) {
+#pragma unroll
+  for (int o = LN / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <int LN>
+__device__ __forceinline__ int f8_group_or(int v) {
+#pragma unroll
+  for (int o = LN / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// LN lanes per particle row (32 for rows of up to 256 markers: two rows per wave, which
+// halves the serial reductions per row), JM = PP / LN coefficients per lane.
+template <int NTERM, int JM, int LN, typename IT>
 __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int p,
                                                           int PP, const double *__restrict__ mu,
                                                           const double *__restrict__ s,
@@ -77,25 +98,25 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
                                                           const double *__restrict__ ytil, uint8_t *__restrict__ Bq,
                                                           int32_t *__restrict__ Bs, double *__restrict__ moff,
                                                           double *__restrict__ yb) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & (LN - 1);
+  const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LN);
   if (i >= M_pad) return;
   double v[JM], used[JM];
   int bad = 0;
 #pragma unroll
   for (int u = 0; u < JM; ++u) {
-    const int j = lane + 64 * u;
+    const int j = lane + LN * u;
     v[u] = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * inv_s[j] * kLog2e : 0.0;
     used[u] = 0.0;
     bad |= !isfinite(v[u]);
   }
-  bad = wave_sum_int(bad);
+  bad = f8_group_or<LN>(bad);
 #pragma unroll
   for (int t = 0; t < NTERM; ++t) {
     double R = 0.0;
 #pragma unroll
     for (int u = 0; u < JM; ++u) R = fmax(R, fabs(v[u] - used[u]));
-    R = wave_max(R);
+    R = f8_group_max<LN>(R);
     int E = 0;
     if (R > 0.0 && isfinite(R)) {
       int k;
@@ -106,7 +127,7 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
     uint8_t *q = Bq + ((size_t)t * M_pad + i) * PP;
 #pragma unroll
     for (int u = 0; u < JM; ++u) {
-      const int j = lane + 64 * u;
+      const int j = lane + LN * u;
       if (j < PP) {
         // scaled residual below 256 in magnitude; the hardware conversion rounds it to the
         // nearest e4m3 value, and the decoded code (the value the MFMA uses) is what counts
@@ -121,14 +142,14 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
   double m = 0.0, ybv = 0.0;
 #pragma unroll
   for (int u = 0; u < JM; ++u) {
-    const int j = lane + 64 * u;
+    const int j = lane + LN * u;
     if (j < PP) {
       m += mu[j] * used[u];
       ybv += ytil[j] * s[j] * used[u];
     }
   }
-  m = wave_sum(m);
-  ybv = wave_sum(ybv);
+  m = f8_group_sum<LN>(m);
+  ybv = f8_group_sum<LN>(ybv);
   if (lane == 0) {
     const double nan = __builtin_nan("");
     moff[i] = bad ? nan : m;
@@ -347,17 +368,16 @@ hipError_t launch_fp8x_pack_x(const uint8_t *X, int n, int p, int n_pad, int PP,
 hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, int M_pad, int p, int PP,
                               const double *mu, const double *s, const double *inv_s, const double *ytil,
                               uint8_t *Bq, int32_t *Bs, double *moff, double *yb, hipStream_t st) {
-  if (PP > 512 || PP % 128 != 0 || M_pad % 4 != 0) return hipErrorInvalidValue;
-  const int grid = M_pad / 4;
-#define SPA_F8PACK(NT_, JM_, IT_)                                                                          \
-  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, JM_, IT_>), dim3(grid), dim3(256), 0, st, (const IT_ *)beta, M, \
-                     M_pad, p, PP, mu, s, inv_s, ytil, Bq, Bs, moff, yb)
-#define SPA_F8PACK_JM(NT_, IT_)                 \
-  switch (PP) {                                 \
-    case 128: SPA_F8PACK(NT_, 2, IT_); break;   \
-    case 256: SPA_F8PACK(NT_, 4, IT_); break;   \
-    case 384: SPA_F8PACK(NT_, 6, IT_); break;   \
-    default: SPA_F8PACK(NT_, 8, IT_); break;    \
+  if (PP > 512 || PP % 128 != 0 || M_pad % 8 != 0) return hipErrorInvalidValue;
+#define SPA_F8PACK(NT_, JM_, LN_, IT_)                                                                       \
+  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, JM_, LN_, IT_>), dim3(M_pad / (256 / (LN_))), dim3(256), 0, st, \
+                     (const IT_ *)beta, M, M_pad, p, PP, mu, s, inv_s, ytil, Bq, Bs, moff, yb)
+#define SPA_F8PACK_JM(NT_, IT_)                     \
+  switch (PP) {                                     \
+    case 128: SPA_F8PACK(NT_, 4, 32, IT_); break;   \
+    case 256: SPA_F8PACK(NT_, 8, 32, IT_); break;   \
+    case 384: SPA_F8PACK(NT_, 6, 64, IT_); break;   \
+    default: SPA_F8PACK(NT_, 8, 64, IT_); break;    \
   }
   if (nterm == 3) {
     if (in_f64) SPA_F8PACK_JM(3, double) else SPA_F8PACK_JM(3, float)
