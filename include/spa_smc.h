@@ -305,8 +305,7 @@ spa_status spa_philox4x32_10(spa_smc *h, const uint32_t *ctr_dev, int32_t M, uin
  */
 enum {
   SPA_T_PROPOSE = 0,    /* proposal + scaled-coefficient operand (first sweep of a   */
-                        /* step; burn-in sweeps; single-coordinate cycles; with the    */
-                        /* FP8 precisions, every sweep's packing into e4m3 terms)      */
+                        /* step; burn-in sweeps; single-coordinate cycles)             */
   SPA_T_LOGLIK = 1,     /* MFMA log-likelihood contraction (+ adjoint for MALA)        */
   SPA_T_ACCEPT = 2,     /* Metropolis-Hastings decisions; within a step, every sweep */
                         /* but the last also draws the next sweep's proposal here      */

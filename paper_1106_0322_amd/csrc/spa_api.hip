@@ -369,9 +369,9 @@ spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad,
 // Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
 // With finalize = false and more than one individual split the partial sums are left for
 // the caller (the MH decision combines them), and *used describes them.
-// time_pack: bracket the packing as the proposal class (the sampler's sweeps).
-spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out,
-                         bool finalize, Fp8xArgs *used, bool time_pack = false) {
+// Buffers of the FP8 multi-term contraction for M particles (grown on demand; the genotype
+// copy is packed once); *PPo / *Mpado receive the padded marker and particle counts.
+spa_status ensure_f8(spa_smc *h, int M, int nterm, int *PPo, int *Mpado) {
   spa_status st;
   const int PP = fp8x_pad_markers(h->p);
   if (PP < 0) return set_err(h, SPA_ERR_ARG, "FP8 multi-term path needs p <= 512");
@@ -381,7 +381,6 @@ spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nt
     SPA_CK(h, launch_fp8x_pack_x(h->dX, h->n, h->p, n_pad, PP, h->f8_X, h->stream));
   }
   const int Mpad = round_up(M, std::max(kPartPad, fp8x_particles_per_wg(PP, nterm)));
-  const int S = fp8x_splits(PP, nterm, n_pad, M);
   if (h->f8_cap < (size_t)Mpad) {
     dfree(h, h->f8_Bq);
     dfree(h, h->f8_Bs);
@@ -399,10 +398,23 @@ spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nt
     if ((st = dalloc(h, &h->f8_part, 8 * 8 * (size_t)Mpad)) != SPA_OK) return st;
     h->f8_cap = Mpad;
   }
-  if (time_pack) tbeg(h, SPA_T_PROPOSE);
-  SPA_CK(h, launch_fp8x_pack_b(nterm, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil,
-                               h->f8_Bq, h->f8_Bs, h->f8_moff, h->f8_yb, h->stream));
-  if (time_pack) tend(h);
+  *PPo = PP;
+  *Mpado = Mpad;
+  return SPA_OK;
+}
+
+// pack = false: the term rows, exponents and offsets of `beta` are already in the buffers
+// (written by the sampler's proposal step).
+spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out,
+                         bool finalize, Fp8xArgs *used, bool pack = true) {
+  spa_status st;
+  int PP = 0, Mpad = 0;
+  if ((st = ensure_f8(h, M, nterm, &PP, &Mpad)) != SPA_OK) return st;
+  const int n_pad = round_up(h->n, kF8Tile);
+  const int S = fp8x_splits(PP, nterm, n_pad, M);
+  if (pack)
+    SPA_CK(h, launch_fp8x_pack_b(nterm, is_f64 != 0, beta, M, Mpad, h->p, PP, h->mu, h->s, h->inv_s, h->ytil,
+                                 h->f8_Bq, h->f8_Bs, h->f8_moff, h->f8_yb, h->stream));
   Fp8xArgs a{};
   a.nterm = nterm;
   a.PP = PP;
@@ -473,6 +485,18 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   pa.k1 = h->k1;
   pa.sweep = static_cast<uint32_t>(s);
   pa.t = t;
+  if (h->f8_terms) {   // random-walk rows write the FP8 term operand instead of BF16 hi/lo
+    int PP8 = 0, Mp8 = 0;
+    spa_status st = ensure_f8(h, h->N, h->f8_terms, &PP8, &Mp8);
+    if (st != SPA_OK) return st;
+    pa.f8_q = h->f8_Bq;
+    pa.f8_s = h->f8_Bs;
+    pa.f8_terms = h->f8_terms;
+    pa.f8_Mp = Mp8;
+    pa.f8_PP = PP8;
+    pa.moff = h->f8_moff;
+    pa.yb = h->f8_yb;
+  }
   if (!have_prop) {
     tbeg(h, SPA_T_PROPOSE);
     launch_propose(h->prec, mala, pa, h->stream);
@@ -481,7 +505,7 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   AcceptArgs aa{};
   if (h->f8_terms) {   // random-walk moves on the FP8 MFMA: the proposal is packed into terms
     Fp8xArgs fa;
-    spa_status st = fp8x_contract(h, h->prop, h->N, 0, h->f8_terms, h->llp, false, &fa, true);
+    spa_status st = fp8x_contract(h, h->prop, h->N, 0, h->f8_terms, h->llp, false, &fa, false);
     if (st != SPA_OK) return st;
     if (fa.S > 1) {
       aa.spl_part = fa.spl_part;

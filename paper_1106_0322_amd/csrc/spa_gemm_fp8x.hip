@@ -88,9 +88,11 @@ __device__ __forceinline__ int f8_group_or(int v) {
   return v;
 }
 
-// LN lanes per particle row (32 for rows of up to 256 markers: two rows per wave, which
-// halves the serial reductions per row), JM = PP / LN coefficients per lane.
-template <int NTERM, int JM, int LN, typename IT>
+// LN lanes per particle row, in the layout of the sampler's move kernels: lane l holds
+// markers 4l + 4 LN kb + k (kb = 0, 1; k = 0..3), LN = 32 (two rows per wave) when p + 1
+// <= 256, else 64.  The sampler's proposal step packs its random-walk proposals with the
+// same arithmetic in the same order, so both give identical codes, exponents and offsets.
+template <int NTERM, int LN, typename IT>
 __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__ beta, int M, int M_pad, int p,
                                                           int PP, const double *__restrict__ mu,
                                                           const double *__restrict__ s,
@@ -98,56 +100,65 @@ __global__ __launch_bounds__(256) void fp8x_pack_b_kernel(const IT *__restrict__
                                                           const double *__restrict__ ytil, uint8_t *__restrict__ Bq,
                                                           int32_t *__restrict__ Bs, double *__restrict__ moff,
                                                           double *__restrict__ yb) {
+  constexpr int KB = 2;
   const int lane = threadIdx.x & (LN - 1);
   const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LN);
   if (i >= M_pad) return;
-  double v[JM], used[JM];
+  double v[KB][4], used[KB][4];
   int bad = 0;
 #pragma unroll
-  for (int u = 0; u < JM; ++u) {
-    const int j = lane + LN * u;
-    v[u] = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * inv_s[j] * kLog2e : 0.0;
-    used[u] = 0.0;
-    bad |= !isfinite(v[u]);
-  }
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = 4 * lane + 4 * LN * kb + k;
+      v[kb][k] = (i < M && j < p) ? static_cast<double>(beta[(size_t)i * p + j]) * inv_s[j] * kLog2e : 0.0;
+      used[kb][k] = 0.0;
+      bad |= !isfinite(v[kb][k]);
+    }
   bad = f8_group_or<LN>(bad);
 #pragma unroll
   for (int t = 0; t < NTERM; ++t) {
     double R = 0.0;
 #pragma unroll
-    for (int u = 0; u < JM; ++u) R = fmax(R, fabs(v[u] - used[u]));
+    for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) R = fmax(R, fabs(v[kb][k] - used[kb][k]));
     R = f8_group_max<LN>(R);
     int E = 0;
     if (R > 0.0 && isfinite(R)) {
-      int k;
-      frexp(R, &k);
-      E = k - 1 - 7;                        // R 2^-E in [128, 256)
+      int e2;
+      frexp(R, &e2);
+      E = e2 - 1 - 7;                       // R 2^-E in [128, 256)
     }
     E = max(-kF8Unit, min(kF8Unit, E));
     uint8_t *q = Bq + ((size_t)t * M_pad + i) * PP;
 #pragma unroll
-    for (int u = 0; u < JM; ++u) {
-      const int j = lane + LN * u;
-      if (j < PP) {
+    for (int kb = 0; kb < KB; ++kb) {
+      const int b0 = 4 * lane + 4 * LN * kb;
+      uint32_t packed = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
         // scaled residual below 256 in magnitude; the hardware conversion rounds it to the
         // nearest e4m3 value, and the decoded code (the value the MFMA uses) is what counts
-        const float x = static_cast<float>(ldexp(v[u] - used[u], -E));
+        const float x = static_cast<float>(ldexp(v[kb][k] - used[kb][k], -E));
         const int c = fabsf(x) >= 1.0f ? (__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF) : 0;
-        q[j] = static_cast<uint8_t>(c);
-        used[u] += ldexp(static_cast<double>(__builtin_amdgcn_cvt_f32_fp8(c, 0)), E);
+        used[kb][k] += ldexp(static_cast<double>(__builtin_amdgcn_cvt_f32_fp8(c, 0)), E);
+        packed |= static_cast<uint32_t>(c) << (8 * k);
       }
+      if (b0 < PP) *reinterpret_cast<uint32_t *>(q + b0) = packed;   // 4-byte aligned
     }
     if (lane == 0) Bs[(size_t)t * M_pad + i] = E + kF8Unit;
   }
   double m = 0.0, ybv = 0.0;
 #pragma unroll
-  for (int u = 0; u < JM; ++u) {
-    const int j = lane + LN * u;
-    if (j < PP) {
-      m += mu[j] * used[u];
-      ybv += ytil[j] * s[j] * used[u];
+  for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int j = 4 * lane + 4 * LN * kb + k;
+      const bool in = j < PP;
+      m += (in ? mu[j] : 0.0) * used[kb][k];
+      ybv += (in ? ytil[j] * s[j] : 0.0) * used[kb][k];
     }
-  }
   m = f8_group_sum<LN>(m);
   ybv = f8_group_sum<LN>(ybv);
   if (lane == 0) {
@@ -369,24 +380,24 @@ hipError_t launch_fp8x_pack_b(int nterm, bool in_f64, const void *beta, int M, i
                               const double *mu, const double *s, const double *inv_s, const double *ytil,
                               uint8_t *Bq, int32_t *Bs, double *moff, double *yb, hipStream_t st) {
   if (PP > 512 || PP % 128 != 0 || M_pad % 8 != 0) return hipErrorInvalidValue;
-#define SPA_F8PACK(NT_, JM_, LN_, IT_)                                                                       \
-  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, JM_, LN_, IT_>), dim3(M_pad / (256 / (LN_))), dim3(256), 0, st, \
+  // lanes per row as in the sampler's move kernels: 32 when p + 1 <= 256
+  const bool narrow = p + 1 <= 256;
+#define SPA_F8PACK(NT_, LN_, IT_)                                                                         \
+  hipLaunchKernelGGL((fp8x_pack_b_kernel<NT_, LN_, IT_>), dim3(M_pad / (256 / (LN_))), dim3(256), 0, st, \
                      (const IT_ *)beta, M, M_pad, p, PP, mu, s, inv_s, ytil, Bq, Bs, moff, yb)
-#define SPA_F8PACK_JM(NT_, IT_)                     \
-  switch (PP) {                                     \
-    case 128: SPA_F8PACK(NT_, 4, 32, IT_); break;   \
-    case 256: SPA_F8PACK(NT_, 8, 32, IT_); break;   \
-    case 384: SPA_F8PACK(NT_, 6, 64, IT_); break;   \
-    default: SPA_F8PACK(NT_, 8, 64, IT_); break;    \
-  }
+#define SPA_F8PACK_LN(NT_, IT_)               \
+  do {                                        \
+    if (narrow) SPA_F8PACK(NT_, 32, IT_);     \
+    else SPA_F8PACK(NT_, 64, IT_);            \
+  } while (0)
   if (nterm == 3) {
-    if (in_f64) SPA_F8PACK_JM(3, double) else SPA_F8PACK_JM(3, float)
+    if (in_f64) SPA_F8PACK_LN(3, double); else SPA_F8PACK_LN(3, float);
   } else if (nterm == 4) {
-    if (in_f64) SPA_F8PACK_JM(4, double) else SPA_F8PACK_JM(4, float)
+    if (in_f64) SPA_F8PACK_LN(4, double); else SPA_F8PACK_LN(4, float);
   } else {
     return hipErrorInvalidValue;
   }
-#undef SPA_F8PACK_JM
+#undef SPA_F8PACK_LN
 #undef SPA_F8PACK
   return hipGetLastError();
 }

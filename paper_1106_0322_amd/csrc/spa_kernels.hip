@@ -251,6 +251,59 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
+template <int LP>
+__device__ __forceinline__ double group_max(double v) {
+#pragma unroll
+  for (int o = LP / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// The FP8 multi-term operand of one random-walk proposal row from its scaled coefficients
+// bv = (beta'/s) log2(e) in the row layout above (zero outside the row): term by term, the
+// exponent puts the largest residual of the row in [128, 256), residual entries of at
+// least 1 in that scale are rounded to e4m3 by the hardware conversion and smaller ones
+// wait for the next term; the decoded codes are what the FP8 MFMA multiplies, and their
+// sum is returned in used.  The standalone packing kernel of the contraction uses the same
+// lane layout and order, so both give identical codes, exponents and offsets.
+template <int LP>
+__device__ __forceinline__ void f8_terms_row(const ProposeArgs &a, const int i, const int lane,
+                                             const double (&bv)[kRowBlocks][4], double (&used)[kRowBlocks][4]) {
+#pragma unroll
+  for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) used[kb][k] = 0.0;
+  for (int t = 0; t < a.f8_terms; ++t) {
+    double R = 0.0;
+#pragma unroll
+    for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) R = fmax(R, fabs(bv[kb][k] - used[kb][k]));
+    R = group_max<LP>(R);
+    int E = 0;
+    if (R > 0.0 && isfinite(R)) {
+      int e2;
+      frexp(R, &e2);
+      E = e2 - 1 - 7;
+    }
+    E = max(-127, min(127, E));
+    uint8_t *q = a.f8_q + ((size_t)t * a.f8_Mp + i) * a.f8_PP;
+#pragma unroll
+    for (int kb = 0; kb < kRowBlocks; ++kb) {
+      const int b0 = lane * 4 + 4 * LP * kb;
+      uint32_t packed = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float x = static_cast<float>(ldexp(bv[kb][k] - used[kb][k], -E));
+        const int c = fabsf(x) >= 1.0f ? (__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF) : 0;
+        used[kb][k] += ldexp(static_cast<double>(__builtin_amdgcn_cvt_f32_fp8(c, 0)), E);
+        packed |= static_cast<uint32_t>(c) << (8 * k);
+      }
+      if (b0 < a.f8_PP) *reinterpret_cast<uint32_t *>(q + b0) = packed;   // 4-byte aligned
+    }
+    if (lane == 0) a.f8_s[(size_t)t * a.f8_Mp + i] = E + 127;
+  }
+}
+
 // The proposal of one particle row (random walk or MALA) from its current coefficients
 // and likelihood gradient (in registers, zero outside the row), the B operand of the
 // proposal and the per-particle log prior terms.  The prior and proposal arithmetic runs
@@ -272,6 +325,17 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
   const PT inv_c = static_cast<PT>(1.0 / pr.lam);
   const PT step = static_cast<PT>(a.step), sqrt_step = static_cast<PT>(a.sqrt_step);
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
+  // FP8 multi-term operand (random-walk rows only): the scaled coefficients are kept until
+  // the row is complete, then split into terms
+  constexpr bool F8OK = (P == Prec::BF16X2) && !MALA;
+  const bool f8 = F8OK && a.f8_terms > 0;
+  double bv[F8OK ? kRowBlocks : 1][4], mu8[F8OK ? kRowBlocks : 1][4], yts8[F8OK ? kRowBlocks : 1][4];
+  if constexpr (F8OK) {
+#pragma unroll
+    for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bv[kb][k] = mu8[kb][k] = yts8[kb][k] = 0.0;
+  }
 #pragma unroll
   for (int kb = 0; kb < kRowBlocks; ++kb) {
     const int b0 = lane * 4 + 4 * LP * kb;
@@ -316,17 +380,29 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
     }
     if (act) store4(prop, vrow, b0, p, nv);
     // B operand of the proposal (zero in padded markers and padded particles)
-    BT hb[4], lb[4];
+    if (f8) {
+      if constexpr (F8OK) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int j = b0 + k;
-      const double bj = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] : 0.0;
-      double used;
-      BPack<P>::put(bj, hb, lb, k, used);
-      m += mu4[k] * used;
-      ybv += yt4[k] * s4[k] * used;
+        for (int k = 0; k < 4; ++k) {
+          const int j = b0 + k;
+          bv[kb][k] = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] * kLog2e : 0.0;
+          mu8[kb][k] = mu4[k];
+          yts8[kb][k] = yt4[k] * s4[k];
+        }
+      }
+    } else {
+      BT hb[4], lb[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int j = b0 + k;
+        const double bj = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] : 0.0;
+        double used;
+        BPack<P>::put(bj, hb, lb, k, used);
+        m += mu4[k] * used;
+        ybv += yt4[k] * s4[k] * used;
+      }
+      store4_b<P>(Bhi, Blo, (size_t)i * PP + b0, hb, lb);
     }
-    store4_b<P>(Bhi, Blo, (size_t)i * PP + b0, hb, lb);
     if (pr.inf) {
       lpc += static_cast<double>(lc);
       lpp += static_cast<double>(lpn);
@@ -335,6 +411,19 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
       lpp += static_cast<double>(fast_log(fp));
     }
     lqf -= static_cast<double>(q);
+  }
+  if constexpr (F8OK) {
+    if (f8) {
+      double used[kRowBlocks][4];
+      f8_terms_row<LP>(a, i, lane, bv, used);
+#pragma unroll
+      for (int kb = 0; kb < kRowBlocks; ++kb)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          m += mu8[kb][k] * used[kb][k];
+          ybv += yts8[kb][k] * used[kb][k];
+        }
+    }
   }
   m = group_sum<LP>(m);
   ybv = group_sum<LP>(ybv);

@@ -29,6 +29,12 @@ struct ProposeArgs {
   int M, M_pad, p, PP;
   uint32_t k0, k1, sweep;
   int t;
+  // Random-walk rows of a handle on the FP8 multi-term contraction (f8_terms = 3 or 4): the
+  // operand is written as f8_terms e4m3 term rows (f8_terms x f8_Mp x f8_PP codes, f8_terms
+  // x f8_Mp biased exponents) instead of BF16 hi/lo, and moff / yb describe those terms.
+  uint8_t *f8_q;
+  int32_t *f8_s;
+  int f8_terms, f8_Mp, f8_PP;
 };
 
 struct AcceptArgs {
