@@ -116,18 +116,23 @@ def test_fp8x_is_refused_for_mala_and_the_gradient():
         SpaSMC(sc, X, y)
 
 
-@pytest.mark.parametrize("prec", ["fp8x3", "fp8x4"])
-def test_fp8x_random_walk_sampler_full_size(prec):
-    """Random-walk sweeps contracting on the FP8 MFMA at the 5000 x 200, 16384-particle
-    shape: the log-likelihoods the sampler keeps are bit-identical to a fresh FP8
-    evaluation of its particles (same packing, same split order), and sampled rows are
-    within 1e-4 of the oracle."""
+@pytest.mark.parametrize("name,n,p,N,init,prec", [
+    ("n5000_p200_rwm_fp32", None, None, None, 4, "fp8x3"),
+    ("n5000_p200_rwm_fp32", None, None, None, 4, "fp8x4"),
+    ("n10000_p500_mala_fp8", None, None, None, 2, "fp8x3"),   # 64 lanes per row
+    ("n2000_p50_rwm_fp32", 2000, 256, 1024, 4, "fp8x3"),       # 64 lanes, 256-marker FP8 rows
+])
+def test_fp8x_random_walk_sampler(name, n, p, N, init, prec):
+    """Random-walk sweeps contracting on the FP8 MFMA (the full 5000 x 200 / 16384 and
+    10000 x 500 / 32768 shapes, and the p = 256 boundary where the move kernels switch to 64
+    lanes per row while the FP8 rows stay 256 wide): the log-likelihoods the sampler keeps
+    (its proposal step writes the term operand) are bit-identical to a fresh evaluation
+    through the standalone packing (same layout, codes, exponents and summation order), and
+    sampled rows are within 1e-4 of the oracle."""
     from paper_1106_0322_amd import SamplerConfig, SpaSMC
-    from synth import CONFIGS
-    torch = _torch()
-    cfg, X, y, Xs = dataset("n5000_p200_rwm_fp32")
-    w = cfg.replace(prec=prec)
-    s = SpaSMC(SamplerConfig.from_workload(w, n=X.shape[0], p=X.shape[1], init_sweeps=4), X, y)
+    cfg, X, y, Xs = dataset(name, n, p)
+    w = cfg.replace(prec=prec, move="rwm", **({"N": N} if N else {}))
+    s = SpaSMC(SamplerConfig.from_workload(w, n=X.shape[0], p=X.shape[1], init_sweeps=init), X, y)
     out = s.step()
     assert math.isfinite(out["ess"]) and 0.0 < out["accept_rate"] < 1.0
     beta, logw = s.particles()
@@ -137,7 +142,8 @@ def test_fp8x_random_walk_sampler_full_size(prec):
     idx = np.random.default_rng(0).choice(w.N, size=48, replace=False)
     ref = likelihood.loglik(beta[idx].double().cpu().numpy(), Xs, y)
     e = rel_err(kept[idx], ref)
-    print(f"{prec} sampler: sampled loglik max rel err {e.max():.3e}, accept {out['accept_rate']:.3f}")
+    print(f"{name} p={X.shape[1]} {prec} sampler: sampled loglik max rel err {e.max():.3e}, "
+          f"accept {out['accept_rate']:.3f}")
     assert e.max() <= 1e-4
     assert np.all(np.isfinite(logw.cpu().numpy()))
     s.close()
