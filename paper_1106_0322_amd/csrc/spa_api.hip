@@ -366,9 +366,6 @@ spa_status run_gemm(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad,
   return SPA_OK;
 }
 
-// Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
-// With finalize = false and more than one individual split the partial sums are left for
-// the caller (the MH decision combines them), and *used describes them.
 // Buffers of the FP8 multi-term contraction for M particles (grown on demand; the genotype
 // copy is packed once); *PPo / *Mpado receive the padded marker and particle counts.
 spa_status ensure_f8(spa_smc *h, int M, int nterm, int *PPo, int *Mpado) {
@@ -403,8 +400,11 @@ spa_status ensure_f8(spa_smc *h, int M, int nterm, int *PPo, int *Mpado) {
   return SPA_OK;
 }
 
-// pack = false: the term rows, exponents and offsets of `beta` are already in the buffers
-// (written by the sampler's proposal step).
+// Forward log-likelihood on the FP8 MFMA with the coefficients split into nterm e4m3 terms.
+// With finalize = false and more than one individual split the partial sums are left for
+// the caller (the MH decision combines them), and *used describes them.  pack = false: the
+// term rows, exponents and offsets of `beta` are already in the buffers (written by the
+// sampler's proposal step).
 spa_status fp8x_contract(spa_smc *h, const void *beta, int M, int is_f64, int nterm, double *out,
                          bool finalize, Fp8xArgs *used, bool pack = true) {
   spa_status st;
