@@ -310,7 +310,9 @@ __device__ __forceinline__ void f8_terms_row(const ProposeArgs &a, const int i, 
 // in the particle precision PT; the log prior of a block of four coefficients is one log
 // of the product of their factors.  `live` is false for padded particles (i >= M), which
 // get a zero operand row.
-template <Prec P, typename PT, bool MALA, int LP>
+// F8: the instance for random-walk rows of a handle on the FP8 multi-term contraction
+// (compiled separately, so the other instances keep their register budget).
+template <Prec P, typename PT, bool MALA, int LP, bool F8 = false>
 __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, const int lane, const bool live,
                                             const PT (&cur)[kRowBlocks][4], const PT (&gv)[kRowBlocks][4]) {
   using BT = typename BPack<P>::BT;
@@ -327,8 +329,8 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
   // FP8 multi-term operand (random-walk rows only): the scaled coefficients are kept until
   // the row is complete, then split into terms
-  constexpr bool F8OK = (P == Prec::BF16X2) && !MALA;
-  const bool f8 = F8OK && a.f8_terms > 0;
+  constexpr bool F8OK = F8 && (P == Prec::BF16X2) && !MALA;
+  constexpr bool f8 = F8OK;
   double bv[F8OK ? kRowBlocks : 1][4], mu8[F8OK ? kRowBlocks : 1][4], yts8[F8OK ? kRowBlocks : 1][4];
   if constexpr (F8OK) {
 #pragma unroll
@@ -468,7 +470,7 @@ __device__ __forceinline__ void store_row(PT *row, const int lane, const int p, 
 }
 
 // One proposal sweep over all (padded) particle rows; LP lanes per particle.
-template <Prec P, typename PT, bool MALA, int LP>
+template <Prec P, typename PT, bool MALA, int LP, bool F8>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
   const int lane = threadIdx.x & (LP - 1);
   const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
@@ -479,7 +481,7 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
   load_row<LP>(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
   if constexpr (MALA) load_row<LP>(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
   else load_row<LP>(static_cast<const PT *>(nullptr), lane, 0, gv);
-  propose_row<P, PT, MALA, LP>(a, i, lane, live, cur, gv);
+  propose_row<P, PT, MALA, LP, F8>(a, i, lane, live, cur, gv);
 }
 
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
 // the row it has just decided (the state after this decision, still in registers), so the
 // next sweep needs no separate proposal launch; valid while the proposal scale, the step
 // size and the prior stay fixed between the two sweeps.
-template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT, int LP>
+template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT, int LP, bool F8>
 __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs na) {
   const int lane = threadIdx.x & (LP - 1);
   const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
@@ -594,7 +596,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
           gv[kb][k] = PT(0);
         }
     }
-    propose_row<P, PT, MALA, LP>(na, i, lane, true, cur, gv);
+    propose_row<P, PT, MALA, LP, F8>(na, i, lane, true, cur, gv);
   }
 }
 
@@ -987,12 +989,12 @@ void launch_pack_b(Prec prec, bool in_f64, const void *beta, int M, int M_pad, i
 // padded row fits in 256 markers.
 static inline int row_lanes(int PP) { return PP <= 256 ? 32 : 64; }
 
-template <Prec P, typename PT, bool MALA>
+template <Prec P, typename PT, bool MALA, bool F8 = false>
 static void launch_propose_t(const ProposeArgs &a, hipStream_t st) {
   if (row_lanes(a.PP) == 32)
-    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32>), dim3(grid_rows(a.M_pad, 8)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32, F8>), dim3(grid_rows(a.M_pad, 8)), dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64>), dim3(grid_rows(a.M_pad, 4)), dim3(256), 0, st, a);
+    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64, F8>), dim3(grid_rows(a.M_pad, 4)), dim3(256), 0, st, a);
 }
 
 void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) {
@@ -1004,20 +1006,21 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) 
     else launch_propose_t<Prec::F32, float, false>(a, st);
   } else {
     if (mala) launch_propose_t<Prec::BF16X2, float, true>(a, st);
+    else if (a.f8_terms > 0) launch_propose_t<Prec::BF16X2, float, false, true>(a, st);
     else launch_propose_t<Prec::BF16X2, float, false>(a, st);
   }
 }
 
-template <Prec P, typename PT, bool MALA, bool NEXT>
+template <Prec P, typename PT, bool MALA, bool NEXT, bool F8 = false>
 static void launch_accept_t(bool parts, int PP, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
   if (row_lanes(PP) == 32) {
     const int grid = grid_rows(a.M, 8);
-    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 32>), dim3(grid), dim3(256), 0, st, a, na);
-    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 32>), dim3(grid), dim3(256), 0, st, a, na);
+    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 32, F8>), dim3(grid), dim3(256), 0, st, a, na);
+    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 32, F8>), dim3(grid), dim3(256), 0, st, a, na);
   } else {
     const int grid = grid_rows(a.M, 4);
-    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 64>), dim3(grid), dim3(256), 0, st, a, na);
-    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 64>), dim3(grid), dim3(256), 0, st, a, na);
+    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 64, F8>), dim3(grid), dim3(256), 0, st, a, na);
+    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 64, F8>), dim3(grid), dim3(256), 0, st, a, na);
   }
 }
 
@@ -1026,6 +1029,12 @@ static void launch_accept_p(bool mala, bool parts, int PP, const AcceptArgs &a, 
                             hipStream_t st) {
   const ProposeArgs none{};
   if (next) {
+    if constexpr (P == Prec::BF16X2) {
+      if (!mala && next->f8_terms > 0) {
+        launch_accept_t<P, PT, false, true, true>(parts, PP, a, *next, st);
+        return;
+      }
+    }
     if (mala) launch_accept_t<P, PT, true, true>(parts, PP, a, *next, st);
     else launch_accept_t<P, PT, false, true>(parts, PP, a, *next, st);
   } else {
