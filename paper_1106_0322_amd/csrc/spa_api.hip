@@ -558,12 +558,15 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   return SPA_OK;
 }
 
-spa_status read_count(spa_smc *h, long long *out) {
-  launch_count(h->acc, h->N, h->dcount, h->stream);
-  SPA_CK(h, hipMemcpyAsync(h->hcount, h->dcount, sizeof(long long), hipMemcpyDeviceToHost, h->stream));
+// Accept count of the sweeps since the counters were zeroed; *nonfinite (nullable) receives
+// the number of particles whose log-likelihood is not finite.
+spa_status read_count(spa_smc *h, long long *out, long long *nonfinite = nullptr) {
+  launch_count(h->acc, h->N, nonfinite ? h->ll : nullptr, h->dcount, h->stream);
+  SPA_CK(h, hipMemcpyAsync(h->hcount, h->dcount, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
   SPA_CK(h, hipStreamSynchronize(h->stream));
   tflush(h);
   *out = h->hcount[0];
+  if (nonfinite) *nonfinite = h->hcount[1];
   return SPA_OK;
 }
 
@@ -1017,8 +1020,9 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
     for (int s = 0; s < h->sweeps; ++s)
       if ((st = sweep(h, t_new, s, lam_new, s > 0, s + 1 < h->sweeps)) != SPA_OK) return st;
   }
-  long long cnt = 0;
-  if ((st = read_count(h, &cnt)) != SPA_OK) return st;
+  long long cnt = 0, bad_ll = 0;
+  if ((st = read_count(h, &cnt, &bad_ll)) != SPA_OK) return st;
+  if (bad_ll) return set_err(h, SPA_ERR_NUMERIC, std::to_string(bad_ll) + " particle(s) with a non-finite log-likelihood");
   if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_summaries(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_map(h, t_new - 1)) != SPA_OK) return st;

@@ -865,18 +865,33 @@ __global__ void moments_final_kernel(const PT *__restrict__ beta, const double *
   if (sigma) sigma[j] = sqrt(fmax(v, sigma_floor * sigma_floor));
 }
 
-__global__ void count_kernel(const int *__restrict__ cnt, int M, long long *__restrict__ out) {
-  __shared__ long long sh[16];
-  long long s = 0;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) s += cnt[i];
+// Accept count of a step, and the number of particles whose log-likelihood is not finite.
+__global__ void count_kernel(const int *__restrict__ cnt, int M, const double *__restrict__ ll,
+                             long long *__restrict__ out) {
+  __shared__ long long sh[2][16];
+  long long s = 0, bad = 0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    s += cnt[i];
+    if (ll && !isfinite(ll[i])) ++bad;
+  }
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    bad += __shfl_xor(bad, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = s;
+    sh[1][threadIdx.x >> 6] = bad;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    long long r = 0;
-    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) r += sh[q];
+    long long r = 0, b = 0;
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+      r += sh[0][q];
+      b += sh[1][q];
+    }
     out[0] = r;
+    out[1] = b;
   }
 }
 
@@ -1097,8 +1112,8 @@ void launch_moments(bool f64, const void *beta, const double *logw, int M, int p
   }
 }
 
-void launch_count(const int *cnt, int M, long long *out, hipStream_t st) {
-  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1024), 0, st, cnt, M, out);
+void launch_count(const int *cnt, int M, const double *ll, long long *out, hipStream_t st) {
+  hipLaunchKernelGGL(count_kernel, dim3(1), dim3(1024), 0, st, cnt, M, ll, out);
 }
 
 void launch_fill(double *x, int n, double v, hipStream_t st) {

@@ -92,7 +92,9 @@ void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void
 int moments_chunks(int M);
 void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
                     double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st);
-void launch_count(const int *cnt, int M, long long *out, hipStream_t st);
+// out[0] = sum of the accept counts; out[1] = particles with a non-finite log-likelihood
+// (ll may be null: 0).
+void launch_count(const int *cnt, int M, const double *ll, long long *out, hipStream_t st);
 void launch_fill(double *x, int n, double v, hipStream_t st);
 void launch_zero_int(int *x, int n, hipStream_t st);
 void launch_convert(bool src_f64, const void *src, void *dst, size_t n, hipStream_t st);

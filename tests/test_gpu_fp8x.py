@@ -75,7 +75,7 @@ def test_fp8x_full_size_sampled(name, M):
     against the oracle one by one."""
     torch = _torch()
     s, cfg, X, y, Xs = _sampler(name)
-    b = particles(M, X.shape[1], seed=7, scale=0.15 if X.shape[1] <= 256 else 0.06)
+    b = particles(M, X.shape[1], seed=7, scale=0.15)
     bt = torch.from_numpy(b).to("cuda", torch.float32)
     idx = np.random.default_rng(1).choice(M, size=256, replace=False)
     ref = likelihood.loglik(bt.double().cpu().numpy()[idx], Xs, y)

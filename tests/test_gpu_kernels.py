@@ -153,6 +153,33 @@ def test_grad_parity(name, prec, M, lam):
         assert rel_err(lp.cpu().numpy(), lp_ref).max() <= ltol
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
+def test_grad_parity_double_exponential(prec):
+    """a = inf (the double-exponential prior, Section 2): prior gradient -sign(b)/lam and
+    log prior -log(2 lam) - |b|/lam, with exact zeros in the coefficients (sign(0) = 0)."""
+    torch = _torch()
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+    cfg, X, y, Xs = dataset("n2000_p50_rwm_fp32")
+    sc = SamplerConfig(n=X.shape[0], p=X.shape[1], N=64, a=math.inf, lambdas=np.geomspace(10, 1, 2),
+                       move="mala", sweeps=0, init_sweeps=0, prec=prec, seed=0)
+    s = SpaSMC(sc, X, y)
+    b = particles(150, X.shape[1], seed=41)
+    lam = 0.2
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    bt = torch.from_numpy(b).to("cuda", dt)
+    bs = bt.double().cpu().numpy()
+    g, lp = s.grad(bt, lam, prec)
+    ll_ref, gl_ref = likelihood.loglik_and_grad(bs, Xs, y)
+    g_ref = gl_ref + gt_prior.gt_grad(bs, math.inf, lam)
+    tol = _grad_tol(prec, Xs) + (2.0 ** -24 * np.abs(g_ref) if dt == torch.float32 else 0.0)
+    err = np.abs(g.double().cpu().numpy() - g_ref)
+    print(f"a=inf {prec}: grad max abs err {err.max():.3e}")
+    assert np.all(err <= tol)
+    lp_ref = ll_ref + gt_prior.log_prior(bs, math.inf, lam)
+    assert rel_err(lp.cpu().numpy(), lp_ref).max() <= (1e-10 if prec == "fp64" else 1e-4)
+    s.close()
+
+
 @pytest.mark.parametrize("n,p,M", [(60, 100, 70), (66, 32, 3), (300, 255, 130), (1000, 200, 257)])
 def test_grad_parity_edge_shapes_bf16(n, p, M):
     """The BF16 adjoint at one split (n <= 64), ragged tails, PP = 64, 224 and 256, and

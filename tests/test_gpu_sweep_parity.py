@@ -1,0 +1,46 @@
+"""Whole-sweep statistical parity at the workloads' stated sizes (Section 4, Section 4.2).
+
+Each workload's full scale grid (T scales, S sweeps per scale, the stated burn-in) runs on
+the GPU from 8 independent Philox keys.  Its posterior-mean path (T x p cells) and its
+log Z_t / Z_1 path are compared with 8 FP64 oracle replicates stored in
+``tests/golden/replicates_<workload>_N<N>.npz``.  ``tests/golden/make_replicates.py`` wrote
+those from ``oracle`` and ``synth`` only.  ``tests/stats_gate.py`` holds the rules:
+* the family-wise Welch-t rule applies at any pair of particle counts;
+* the exact permutation rule is added when the GPU runs at the oracle's particle count.
+The GPU runs in the precision the workload names: FP32 random walk, BF16 hi+lo from FP8
+storage, the FP8 three-term random walk, BF16 hi+lo MALA, and MALA on FP8 storage.
+"""
+import numpy as np
+import pytest
+
+from synth import CONFIGS, make_dataset
+from tests.replicate_util import check_fixture, compare, failed, gpu_replicates, load_fixture
+
+pytestmark = pytest.mark.gpu
+
+# (case id, workload whose data and oracle fixture are used, GPU overrides, oracle N, GPU N)
+CASES = [
+    ("n2000_p50_rwm_fp32", "n2000_p50_rwm_fp32", {}, 8192, 8192),
+    ("n2000_p50_rwm_bf16x2_fp8storage", "n2000_p50_rwm_fp32", dict(prec="bf16x2", xfmt="fp8"), 8192, 8192),
+    ("n2000_p50_rwm_fp8x3", "n2000_p50_rwm_fp32", dict(prec="fp8x3"), 8192, 8192),
+    ("n5000_p200_mala_bf16_full", "n5000_p200_mala_bf16", {}, 4096, 16384),
+    ("n5000_p200_mala_bf16_N4096", "n5000_p200_mala_bf16", {}, 4096, 4096),
+    ("n10000_p500_mala_fp8_full", "n10000_p500_mala_fp8", {}, 1024, 32768),
+    ("n10000_p500_mala_fp8_N1024", "n10000_p500_mala_fp8", {}, 1024, 1024),
+]
+
+
+@pytest.mark.parametrize("case,workload,over,N_orc,N_gpu", CASES, ids=[c[0] for c in CASES])
+def test_sweep_parity(case, workload, over, N_orc, N_gpu):
+    fx = load_fixture(f"{workload}_N{N_orc}")
+    base = CONFIGS[workload]
+    d = make_dataset(base)
+    check_fixture(fx, base, d.X, d.y)
+    assert int(fx["N"]) == N_orc
+    cfg = base.replace(N=N_gpu, **over)
+    om, oz = fx["mean"], fx["log_z"]
+    gm, gz = gpu_replicates(cfg, d.X, d.y, om.shape[0])
+    assert gm.shape == om.shape and gz.shape == oz.shape
+    assert np.all(np.isfinite(gm)) and np.all(np.isfinite(gz))
+    res = compare(case, gm, om, gz, oz, exchangeable=N_gpu == N_orc)
+    assert not failed(res), failed(res)
