@@ -150,6 +150,28 @@ spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M, int32_t b
                           spa_prec prec, double *loglik_dev);
 
 /*
+ * spa_smc_loglik_noalloc -- spa_smc_loglik without any device allocation, for callers
+ * that cannot allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, kernels and results (bit-identical to
+ * spa_smc_loglik at the same prec) for prec SPA_PREC_FP64, SPA_PREC_FP32 or
+ * SPA_PREC_BF16X2; no host synchronisation.  The scaled-coefficient operand, its offsets
+ * and the contraction's split partial sums live in one static device array of 32 MiB per
+ * GPU (held until the process ends), whose address the library takes at spa_smc_init.
+ * Every call on a GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other handles, other threads) race and must be ordered by the caller.  The
+ * array needs, per particle row (M rounded up to 128), PP * 4 bytes (BF16X2: hi and lo),
+ * PP * 4 (FP32) or PP * 8 (FP64) plus 16 bytes of offsets and 8 bytes per individual
+ * split of the contraction, PP being p + 1 rounded up to the contraction's width (at
+ * p = 200 in BF16X2 about 36000 particles fit).
+ * Errors: as spa_smc_loglik; SPA_ERR_ARG also for the FP8 multi-term precisions and for
+ * an M whose buffers exceed the array (the message gives the bytes needed);
+ * SPA_ERR_STATE if the genotype copy of prec has not been prepared (the handle's own
+ * precision always is; another one after one spa_smc_loglik call with it).
+ */
+spa_status spa_smc_loglik_noalloc(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
+                                  spa_prec prec, double *loglik_dev);
+
+/*
  * spa_smc_grad -- gradient of the log posterior at scale lambda for M particles:
  * X_std^T (y - logit^-1(X_std beta_i)) + d/dbeta log Gt(beta_i | a, lambda), the prior part
  * being -(a+1) sign(beta_ij)/(a lambda + |beta_ij|) (-sign(beta_ij)/lambda when a = inf),

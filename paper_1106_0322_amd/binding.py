@@ -26,7 +26,8 @@ XFMT = {"auto": 0, "fp8": 1, "bf16": 2}
 MOVE = {"rwm": 0, "mala": 1, "single": 2}
 
 # The exported C entry points (kept in step with include/spa_smc.h).
-EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_grad", "spa_smc_resample",
+EXPORTS = ["spa_smc_init", "spa_smc_step", "spa_smc_loglik", "spa_smc_loglik_noalloc", "spa_smc_grad",
+           "spa_smc_resample",
            "spa_weighted_summaries", "spa_smc_set_summaries", "spa_smc_get_summaries",
            "spa_smc_marginal_summaries", "spa_map_em", "spa_smc_set_map", "spa_smc_get_map",
            "spa_smc_get", "spa_smc_get_loglik", "spa_smc_get_stats", "spa_smc_set_state",
@@ -82,6 +83,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.spa_smc_init.argtypes = [ctypes.POINTER(_Config), vp, vp, vp, ctypes.POINTER(vp)]
     lib.spa_smc_step.argtypes = [vp, ctypes.POINTER(_Stats)]
     lib.spa_smc_loglik.argtypes = [vp, vp, i32, i32, ctypes.c_int, vp]
+    lib.spa_smc_loglik_noalloc.argtypes = [vp, vp, i32, i32, ctypes.c_int, vp]
     lib.spa_smc_grad.argtypes = [vp, vp, i32, i32, dbl, ctypes.c_int, vp, vp]
     lib.spa_smc_resample.argtypes = [vp, vp, i32, ctypes.c_uint32, vp]
     dptr = ctypes.POINTER(ctypes.c_double)
@@ -283,6 +285,17 @@ class SpaSMC:
         self._check(self.lib.spa_smc_loglik(self.h, _ptr(beta), beta.shape[0],
                                             int(beta.dtype == torch.float64),
                                             PREC[prec or self.cfg.prec], _ptr(out)))
+        return out
+
+    def loglik_noalloc(self, beta, out, prec: Optional[str] = None):
+        """spa_smc_loglik_noalloc into the caller's `out` (M doubles on the device): the
+        library allocates nothing (its scratch is a static device array per GPU)."""
+        torch = _torch()
+        assert beta.is_cuda and beta.is_contiguous() and beta.dim() == 2 and beta.shape[1] == self.cfg.p
+        assert out.is_cuda and out.is_contiguous() and out.dtype == torch.float64 and out.numel() >= beta.shape[0]
+        self._check(self.lib.spa_smc_loglik_noalloc(self.h, _ptr(beta), beta.shape[0],
+                                                    int(beta.dtype == torch.float64),
+                                                    PREC[prec or self.cfg.prec], _ptr(out)))
         return out
 
     def grad(self, beta, lam: float, prec: Optional[str] = None, want_logpost: bool = True):

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -19,12 +20,23 @@
 
 using namespace spa;
 
+// Device scratch of spa_smc_loglik_noalloc (operand rows, offsets and split partials).
+// Each GPU the library runs on holds its own copy until the process ends.  Host code never
+// passes the array's name to a kernel: it uses the device address taken per device with
+// hipGetSymbolAddress at handle creation (noalloc_setup).
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
 
 thread_local std::string g_init_error;
 
 constexpr int kMaxPP = 512;
 constexpr double kSigmaFloor = 1e-12;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 int ceil_log2(long long m) {
@@ -111,6 +123,7 @@ struct spa_smc {
   size_t g_part_cap = 0;
   double *llscr = nullptr;
   size_t llscr_cap = 0;
+  void *noalloc = nullptr;       // this device's address of the static scratch array
   // FP8 multi-term forward contraction (loglik calls, and the contraction of random-walk
   // sweeps when the handle's precision is one of the FP8 ones)
   int f8_terms = 0;              // 3 or 4 when the sampler contracts on the FP8 MFMA
@@ -295,9 +308,9 @@ spa_status ensure_op(spa_smc *h, OpScratch &o, Prec prec, int PP, size_t rows) {
   return SPA_OK;
 }
 
-// Arguments of one contraction launch; allocates the split partials on first need.
-spa_status gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g,
-                     GemmArgs *out) {
+// Arguments of one contraction launch without its partial-sum buffers (a.S tells whether
+// they are needed: S x M_pad softplus sums, and for the gradient S x M_pad x PP adjoints).
+GemmArgs gemm_args_core(const spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g) {
   const XPack &x = h->xp[static_cast<int>(prec)];
   GemmArgs a{};
   a.prec = prec;
@@ -323,6 +336,14 @@ spa_status gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad
   a.g = g;
   const size_t es = prec == Prec::F64 ? 8 : prec == Prec::F32 ? 4 : (x.fp8 ? 1 : 2);
   a.S = gemm_splits(prec, x.PP, h->n_pad, M, 2 * es * (size_t)h->n_pad * x.PP);
+  return a;
+}
+
+// Arguments of one contraction launch; allocates the split partials on first need.
+spa_status gemm_args(spa_smc *h, Prec prec, const OpScratch &o, int M, bool grad, double *ll, void *g,
+                     GemmArgs *out) {
+  const XPack &x = h->xp[static_cast<int>(prec)];
+  GemmArgs a = gemm_args_core(h, prec, o, M, grad, ll, g);
   if ((size_t)a.M_pad > o.cap) return set_err(h, SPA_ERR_ARG, "operand rows not padded");
   if (a.S > 1) {
     spa_status st;
@@ -764,6 +785,48 @@ spa_status parse_levels(spa_smc *h, const double *levels, int32_t L, const doubl
   return SPA_OK;
 }
 
+// This device's address of the static scratch array, taken once per device (with that
+// device current) and kept for the rest of the process.
+spa_status noalloc_setup(spa_smc *h) {
+  if (h->device < 0 || h->device >= kMaxDevices) return set_err(h, SPA_ERR_STATE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[h->device]) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return set_err(h, SPA_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[h->device] = ptr;
+  }
+  h->noalloc = g_scratch_ptr[h->device];
+  return SPA_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Byte offsets, inside the static scratch, of the operand and partial sums of an
+// M-particle contraction at precision prec: Bhi, Blo, moff, yb, spl_part; returns the total.
+size_t noalloc_layout(const spa_smc *h, Prec prec, int M, size_t off[5]) {
+  const int PP = h->xp[static_cast<int>(prec)].PP;
+  const size_t Mpad = static_cast<size_t>(round_up(M, kPartPad));
+  const size_t bs = bt_size(prec);
+  OpScratch probe{};
+  probe.PP = PP;
+  probe.cap = Mpad;
+  const GemmArgs a = gemm_args_core(h, prec, probe, M, false, nullptr, nullptr);
+  size_t at = 0;
+  off[0] = at;
+  at = align256(at + bs * Mpad * PP);
+  off[1] = at;
+  at = align256(at + (prec == Prec::BF16X2 ? bs * Mpad * PP : 0));
+  off[2] = at;
+  at = align256(at + 8 * Mpad);
+  off[3] = at;
+  at = align256(at + 8 * Mpad);
+  off[4] = at;
+  at = align256(at + (a.S > 1 ? 8 * (size_t)a.S * a.M_pad : 0));
+  return at;
+}
+
 spa_status validate_cfg(const spa_smc_config *c) {
   if (!c) return set_err(nullptr, SPA_ERR_ARG, "cfg is NULL");
   if (c->n < 1 || c->p < 1 || c->N < 1) return set_err(nullptr, SPA_ERR_SHAPE, "n, p and N must be >= 1");
@@ -860,6 +923,7 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
     hip_fail(h, he, "hipGetDevice");
     return fail(SPA_ERR_HIP);
   }
+  if ((st = noalloc_setup(h)) != SPA_OK) return fail(st);
   const size_t NP = (size_t)h->Npad * p;
   const bool mala = h->move == SPA_MOVE_MALA;
 #define SPA_AL(ptr, bytes) \
@@ -1076,6 +1140,43 @@ extern "C" spa_status spa_smc_loglik(spa_smc *h, const void *beta_dev, int32_t M
   spa_status st;
   if ((st = prep_operand(h, beta_dev, M, beta_is_fp64, P)) != SPA_OK) return st;
   return run_gemm(h, P, h->scr[static_cast<int>(P)], M, false, loglik_dev, nullptr);
+}
+
+extern "C" spa_status spa_smc_loglik_noalloc(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,
+                                             spa_prec prec, double *loglik_dev) {
+  if (!h) return set_err(nullptr, SPA_ERR_ARG, "handle is NULL");
+  if (!beta_dev || !loglik_dev || M < 1) return set_err(h, SPA_ERR_ARG, "null pointer or M < 1");
+  if (!valid_prec(prec)) return set_err(h, SPA_ERR_ARG, "bad prec (FP64, FP32 or BF16X2 without allocation)");
+  if (prec == SPA_PREC_FP64 && h->p > 255) return set_err(h, SPA_ERR_ARG, "FP64 path needs p <= 255");
+  const Prec P = to_prec(prec);
+  const XPack &x = h->xp[static_cast<int>(P)];
+  if (!x.ready)
+    return set_err(h, SPA_ERR_STATE, "genotype copy of this precision not prepared (call spa_smc_loglik with it once)");
+  if (!h->noalloc) return set_err(h, SPA_ERR_STATE, "no scratch address for this device");
+  size_t off[5];
+  const size_t need = noalloc_layout(h, P, M, off);
+  if (need > kNoAllocBytes)
+    return set_err(h, SPA_ERR_ARG, "M too large for the static scratch (" + std::to_string(need) + " bytes needed, " +
+                                       std::to_string(kNoAllocBytes) + " available)");
+  char *base = static_cast<char *>(h->noalloc);
+  OpScratch o{};
+  o.Bhi = base + off[0];
+  o.Blo = base + (P == Prec::BF16X2 ? off[1] : off[0]);
+  o.moff = reinterpret_cast<double *>(base + off[2]);
+  o.yb = reinterpret_cast<double *>(base + off[3]);
+  o.cap = static_cast<size_t>(round_up(M, kPartPad));
+  o.PP = x.PP;
+  // every padded row and column of the operand is written here, and the contraction writes
+  // every partial it reads, so nothing left by an earlier call is read
+  launch_pack_b(P, beta_is_fp64 != 0, beta_dev, M, static_cast<int>(o.cap), h->p, o.PP, h->mu, h->s, h->inv_s,
+                h->ytil, o.Bhi, o.Blo, o.moff, o.yb, h->stream);
+  SPA_CK(h, hipGetLastError());
+  GemmArgs a = gemm_args_core(h, P, o, M, false, loglik_dev, nullptr);
+  if ((size_t)a.M_pad > o.cap) return set_err(h, SPA_ERR_ARG, "operand rows not padded");
+  if (a.S > 1) a.spl_part = reinterpret_cast<double *>(base + off[4]);
+  SPA_CK(h, launch_loglik(a, h->stream));
+  if (a.S > 1) SPA_CK(h, launch_gemm_finalize(a, h->stream));
+  return SPA_OK;
 }
 
 extern "C" spa_status spa_smc_grad(spa_smc *h, const void *beta_dev, int32_t M, int32_t beta_is_fp64,

@@ -122,6 +122,7 @@ def test_invalid_data_rejected_on_host(lib):
 def test_null_handle_calls(lib):
     assert lib.spa_smc_step(None, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_loglik(None, None, 1, 0, 0, None) == binding.SPA_ERR_ARG
+    assert lib.spa_smc_loglik_noalloc(None, None, 1, 0, 0, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_grad(None, None, 1, 0, 1.0, 0, None, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_resample(None, None, 1, 0, None) == binding.SPA_ERR_ARG
     assert lib.spa_smc_set_state(None, None, None, 1, 1.0) == binding.SPA_ERR_ARG
