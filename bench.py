@@ -182,6 +182,53 @@ def precision_legs(torch, s, cfg, reps: int = 20):
     return out
 
 
+def bandwidth_leg(cfg, X, y, reps: int = 10):
+    """The weight, resampling and moment kernels at the workload's N and p, timed with HIP
+    events per class: steps without moves from given states, alternately with spread
+    log weights (ESS below the threshold: the resampling passes and the gather run) and
+    with nearly equal ones (no resampling: the moment pass also normalises the weights).
+    Rates are algorithmic bytes per launch over the class's average launch time (the
+    reweighting pass and its one-workgroup combination count as one launch, and so do the
+    quantisation, scan and search + gather passes; the moments are two launches per step,
+    the partial sums and their ordered combination)."""
+    import torch
+    from paper_1106_0322_amd import SamplerConfig, SpaSMC
+
+    N, p = cfg.N, cfg.p
+    es = 8 if cfg.prec == "fp64" else 4
+    g = SpaSMC(SamplerConfig.from_workload(cfg, sweeps=0, init_sweeps=0), X, y)
+    rng = np.random.default_rng(0)
+    beta = torch.from_numpy(np.clip(rng.normal(0, 0.1, size=(N, p)), -2, 2)).to(
+        torch.float64 if es == 8 else torch.float32)
+    states = []
+    for k in range(2):
+        lw = rng.normal(0, 2.0 if k == 0 else 0.05, size=N)
+        lw -= np.log(np.exp(lw - lw.max()).sum()) + lw.max()
+        states.append(torch.from_numpy(lw))
+    g.set_timing(True, classes=["reweight", "lse_resample", "moments"])
+    resampled = 0
+    for r in range(2 * reps):
+        g.set_state(beta, states[r % 2], 40, 0.1)
+        resampled += int(g.step()["resampled"])
+    t = g.timing()
+    g.close()
+    mala = cfg.move == "mala"
+    rows = N * p * es
+    by = {"reweight": rows + 16 * N,                                  # beta, log w read + written
+          "lse_resample": 2 * rows * (2 if mala else 1) + 8 * N * 6,  # rows (+ gradients) read and written;
+                                                                      # log w, q/C written and read, ll moved
+          "moments": rows + 16 * N}                                   # beta, log w (+ normalised write)
+    out = {"what": f"N={N} p={p} {cfg.prec} particles, {2 * reps} steps without moves, {resampled} resampling"}
+    for k, b in by.items():
+        ms, n = t[k]
+        if not n:
+            continue
+        us = ms / n * 1e3
+        out[k] = {"us_per_launch": round(us, 2), "launches": n, "algorithmic_bytes": b,
+                  "GBps": round(b / (us * 1e-6) / 1e9, 1), "frac_of_hbm": round(b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def gemm_flops(cfg) -> float:
     """Algorithmic flops of one sweep's contraction: loglik 2Nnp, + adjoint 2Nnp for MALA."""
     f = 2.0 * cfg.N * cfg.n * cfg.p
@@ -289,6 +336,9 @@ def main():
     ap.add_argument("--no-single", action="store_true", help="skip the single-coordinate kernel leg")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the forward-contraction comparison of BF16 hi+lo and the FP8 splits")
+    ap.add_argument("--no-bandwidth", action="store_true", help="skip the weight / resampling / moment kernel leg")
+    ap.add_argument("--bandwidth-only", action="store_true",
+                    help="only run the weight / resampling / moment kernel leg and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference "
                          "launch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -311,6 +361,11 @@ def main():
     if args.prec is not None or args.move is not None:
         cfg = cfg.replace(prec=args.prec or cfg.prec, move=args.move or cfg.move)
         prof_key = None
+    if args.bandwidth_only:
+        d = make_dataset(cfg)
+        torch.cuda.set_device(0)
+        print(json.dumps(bandwidth_leg(cfg, d.X, d.y)))
+        return
     if args.steps + args.warmup + BREAKDOWN_STEPS > cfg.T - 1:
         sys.exit(f"steps + warmup must be <= {cfg.T - 1 - BREAKDOWN_STEPS} scales")
     d = make_dataset(cfg)
@@ -378,6 +433,8 @@ def main():
         "accept_rate": round(float(np.mean([x["accept_rate"] for x in stats])), 4),
     }
     out["analysis"] = analysis_legs(torch, s, cfg)
+    if not args.no_bandwidth:
+        out["bandwidth_kernels"] = bandwidth_leg(cfg, d.X, d.y)
     if not args.no_precision:
         out["precision_variants"] = precision_legs(torch, s, cfg)
     s.close()

@@ -331,9 +331,11 @@ enum {
   SPA_T_LOGLIK = 1,     /* MFMA log-likelihood contraction (+ adjoint for MALA)        */
   SPA_T_ACCEPT = 2,     /* Metropolis-Hastings decisions; within a step, every sweep */
                         /* but the last also draws the next sweep's proposal here      */
-  SPA_T_REWEIGHT = 3,   /* prior-ratio incremental weights                             */
-  SPA_T_LSE = 4,        /* logsumexp / ESS / systematic resampling                     */
-  SPA_T_GATHER = 5,     /* particle gather after resampling                            */
+  SPA_T_REWEIGHT = 3,   /* prior-ratio incremental weights with the logsumexp / ESS    */
+                        /* partials and their combination (one launch)                 */
+  SPA_T_LSE = 4,        /* systematic resampling when triggered: quantised weights,    */
+                        /* exact CDF scan, offspring search with the particle gather   */
+  SPA_T_GATHER = 5,     /* (no launches: the gather is part of SPA_T_LSE)              */
   SPA_T_MOMENTS = 6,    /* weighted moments                                            */
   SPA_T_FINALIZE = 7,   /* ordered sum of the contraction's split partials             */
   SPA_T_SUMMARY = 8,    /* sparsity-path summaries (quantiles, concentrations)         */

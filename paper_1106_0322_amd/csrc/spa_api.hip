@@ -111,6 +111,8 @@ struct spa_smc {
   double *sigma = nullptr, *mean_path = nullptr, *var_path = nullptr, *part = nullptr;
   double *cdf = nullptr, *scal = nullptr;
   size_t cdf_cap = 0;
+  double *rw_part = nullptr;     // workgroup partials of the reweighting pass
+  double *btot = nullptr, *wpart = nullptr;   // resampling pass scratch
   long long *dcount = nullptr;
   double *hscal = nullptr;       // pinned host
   long long *hcount = nullptr;   // pinned host
@@ -602,7 +604,7 @@ void adapt_step(spa_smc *h, double acc_rate) {
 
 spa_status record_moments(spa_smc *h, int row) {
   tbeg(h, SPA_T_MOMENTS);
-  launch_moments(h->f64, h->beta, h->logw, h->N, h->p, h->part, h->mean_path + (size_t)row * h->p,
+  launch_moments(h->f64, h->beta, h->logw, nullptr, h->N, h->p, h->part, h->mean_path + (size_t)row * h->p,
                  h->var_path + (size_t)row * h->p, nullptr, kSigmaFloor, h->stream);
   tend(h);
   SPA_CK(h, hipGetLastError());
@@ -956,6 +958,9 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   SPA_AL(h->part, 8 * 3 * (size_t)moments_chunks(h->N) * p);
   SPA_AL(h->cdf, 8 * (size_t)h->Npad);
   h->cdf_cap = h->Npad;
+  SPA_AL(h->rw_part, 8 * 3 * (size_t)reweight_blocks(h->Npad, p));
+  SPA_AL(h->btot, 8 * (size_t)kResampleBlocks);
+  SPA_AL(h->wpart, 8 * 2 * (size_t)kResampleBlocks);
   SPA_AL(h->scal, 8 * 16);
   SPA_AL(h->dcount, 16);
 #undef SPA_AL
@@ -996,7 +1001,7 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   }
   for (int s = 0; s < (h->move == SPA_MOVE_SINGLE ? 0 : h->init_sweeps); ++s) {
     if (s == h->init_sweeps / 2) {
-      launch_moments(h->f64, h->beta, h->logw, h->N, p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
+      launch_moments(h->f64, h->beta, h->logw, nullptr, h->N, p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
                      h->stream);
     }
     launch_zero_int(h->acc, h->N, h->stream);
@@ -1038,21 +1043,20 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   spa_status st;
 
   // ---- incremental weights, normalisation, ESS, resampling decision (Section 4)
+  ReweightArgs ra{};
+  ra.beta = h->beta;
+  ra.M = h->N;
+  ra.p = h->p;
+  ra.a = h->a;
+  ra.a_inf = h->a_inf;
+  ra.lam_new = lam_new;
+  ra.lam_old = lam_old;
+  ra.ess_frac = h->ess_frac;
+  ra.logw = h->logw;
+  ra.part = h->rw_part;
+  ra.scalars = h->scal;
   tbeg(h, SPA_T_REWEIGHT);
-  launch_reweight(h->f64, h->beta, h->N, h->p, h->a, h->a_inf, lam_new, lam_old, h->logw, h->stream);
-  tend(h);
-  LseArgs la{};
-  la.mode = 0;
-  la.M = h->N;
-  la.K = 53 - ceil_log2(h->N);
-  la.ess_frac = h->ess_frac;
-  la.logw = h->logw;
-  la.cdf = h->cdf;
-  la.anc = h->anc;
-  la.scalars = h->scal;
-  la.u32 = philox_w0(0, 0, 0, (static_cast<uint32_t>(t_new) << 4) | 2u, h->k0, h->k1);
-  tbeg(h, SPA_T_LSE);
-  launch_lse_resample(la, h->stream);
+  launch_reweight(h->f64, ra, h->stream);
   tend(h);
   SPA_CK(h, hipGetLastError());
   SPA_CK(h, hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1061,20 +1065,39 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   const double ess = h->hscal[0], L = h->hscal[1];
   const bool resampled = h->hscal[2] != 0.0;
   if (h->hscal[4] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "non-finite weights");
-  if (resampled) {
-    if (h->hscal[5] != 0.0) return set_err(h, SPA_ERR_NUMERIC, "invalid weights in resampling");
-    tbeg(h, SPA_T_GATHER);
-    launch_gather(h->f64, h->anc, h->N, h->p, h->beta, h->tmp, mala ? h->gl : nullptr, mala ? h->gltmp : nullptr,
-                  h->ll, h->lltmp, h->stream);
+  if (resampled) {   // systematic resampling and the gather; log weights become -log N
+    ResampleArgs rs{};
+    rs.mode = 0;
+    rs.M = h->N;
+    rs.K = 53 - ceil_log2(h->N);
+    rs.u32 = philox_w0(0, 0, 0, (static_cast<uint32_t>(t_new) << 4) | 2u, h->k0, h->k1);
+    rs.logw = h->logw;
+    rs.logw_eq = -std::log(static_cast<double>(h->N));
+    rs.cdf = h->cdf;
+    rs.btot = h->btot;
+    rs.wpart = h->wpart;
+    rs.scalars = h->scal;
+    rs.anc = h->anc;
+    rs.p = h->p;
+    rs.src = h->beta;
+    rs.dst = h->tmp;
+    rs.gsrc = mala ? h->gl : nullptr;
+    rs.gdst = mala ? h->gltmp : nullptr;
+    rs.llsrc = h->ll;
+    rs.lldst = h->lltmp;
+    tbeg(h, SPA_T_LSE);
+    launch_resample(h->f64, rs, h->stream);
     tend(h);
+    SPA_CK(h, hipGetLastError());
     std::swap(h->beta, h->tmp);
     if (mala) std::swap(h->gl, h->gltmp);
     std::swap(h->ll, h->lltmp);
   }
-  // ---- preconditioner from the reweighted cloud, then the moves targeting pi_t
+  // ---- preconditioner from the reweighted cloud (normalising the log weights by L
+  // unless resampling reset them), then the moves targeting pi_t
   tbeg(h, SPA_T_MOMENTS);
-  launch_moments(h->f64, h->beta, h->logw, h->N, h->p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
-                 h->stream);
+  launch_moments(h->f64, h->beta, h->logw, resampled ? nullptr : h->scal + 1, h->N, h->p, h->part, nullptr, nullptr,
+                 h->sigma, kSigmaFloor, h->stream);
   tend(h);
   launch_zero_int(h->acc, h->N, h->stream);
   const double step_used = h->step;
@@ -1227,16 +1250,18 @@ extern "C" spa_status spa_smc_resample(spa_smc *h, const double *w_dev, int32_t 
     if ((st = dalloc(h, &h->cdf, 8 * (size_t)M)) != SPA_OK) return st;
     h->cdf_cap = M;
   }
-  LseArgs la{};
-  la.mode = 1;
-  la.M = M;
-  la.K = 53 - ceil_log2(M);
-  la.w = w_dev;
-  la.cdf = h->cdf;
-  la.anc = ancestors_dev;
-  la.scalars = h->scal;
-  la.u32 = u32;
-  launch_lse_resample(la, h->stream);
+  ResampleArgs rs{};
+  rs.mode = 1;
+  rs.M = M;
+  rs.K = 53 - ceil_log2(M);
+  rs.u32 = u32;
+  rs.w = w_dev;
+  rs.cdf = h->cdf;
+  rs.btot = h->btot;
+  rs.wpart = h->wpart;
+  rs.scalars = h->scal;
+  rs.anc = ancestors_dev;
+  launch_resample(false, rs, h->stream);
   SPA_CK(h, hipGetLastError());
   SPA_CK(h, hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   SPA_CK(h, hipStreamSynchronize(h->stream));

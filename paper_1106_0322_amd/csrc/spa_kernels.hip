@@ -602,238 +602,452 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
 
 // ================================================================ weights
 
-// logw_i += sum_j [log Gt(beta_ij | a, lam_new) - log Gt(beta_ij | a, lam_old)], in FP64:
-//   = p a log r - (a+1) log prod_j (a lam_new + |b_ij|)/(a lam_old + |b_ij|),  r = lam_new/lam_old,
-// each lane forming the product of its (at most 8) ratios, all in (r, 1], before one log;
-// the double exponential: p log(1/r) - (1/lam_new - 1/lam_old) sum_j |b_ij|.
-template <typename PT>
-__global__ void reweight_kernel(const PT *__restrict__ beta, int M, int p, double a, int a_inf,
-                                double lam_new, double lam_old, double *__restrict__ logw) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= M) return;
-  const double lr = log(lam_new / lam_old);
-  double d = 0.0;
-  if (a_inf) {
-    double sx = 0.0;
-    for (int j = lane; j < p; j += 64) sx += fabs(static_cast<double>(beta[(size_t)i * p + j]));
-    d = -(1.0 / lam_new - 1.0 / lam_old) * sx;
-  } else {
-    const double an = a * lam_new, ao = a * lam_old;
-    double prod = 1.0;
-    for (int j = lane; j < p; j += 64) {
-      const double x = fabs(static_cast<double>(beta[(size_t)i * p + j]));
-      prod *= (an + x) / (ao + x);
-    }
-    d = -(a + 1.0) * log(prod);
-  }
-  d = wave_sum(d);
-  if (lane == 0) logw[i] += d + static_cast<double>(p) * (a_inf ? -lr : a * lr);
-}
+// Lanes per particle row of the weight, resampling-gather and moment passes: the fewest
+// (8, 16, 32 or 64) for which a lane holds at most two blocks of four coefficients.
+static __host__ __device__ constexpr int bw_lanes(int p) { return p <= 64 ? 8 : p <= 128 ? 16 : p <= 256 ? 32 : 64; }
+constexpr int kBW = 256;   // threads per workgroup of the bandwidth kernels
 
-// ---- single-workgroup reductions (1024 threads, fixed order)
-constexpr int kRB = 1024;
-
-__device__ double block_max(double v, double *sh) {
+// Fixed-order workgroup reductions of one value per thread over WG threads (every thread
+// gets the result); sh holds WG / kWave doubles.
+template <int WG = kBW>
+__device__ double wg_max(double v, double *sh) {
   v = wave_max(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
   __syncthreads();
   double r = sh[0];
-  for (int q = 1; q < kRB / 64; ++q) r = fmax(r, sh[q]);
+  for (int q = 1; q < WG / kWave; ++q) r = fmax(r, sh[q]);
   return r;
 }
-__device__ double block_sum(double v, double *sh) {
+template <int WG = kBW>
+__device__ double wg_sum(double v, double *sh) {
   v = wave_sum(v);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();
-  if (lane == 0) sh[w] = v;
+  if ((threadIdx.x & (kWave - 1)) == 0) sh[threadIdx.x / kWave] = v;
   __syncthreads();
   double r = sh[0];
-  for (int q = 1; q < kRB / 64; ++q) r += sh[q];
+  for (int q = 1; q < WG / kWave; ++q) r += sh[q];
   return r;
 }
 
-// Normalisation, log Z increment, ESS and (if triggered, or always in weight mode)
-// systematic resampling of the quantised CDF.
-//  mode 0: input logw (log weights relative to the normalised logW_{t-1}); writes the
-//          normalised logW, scalars {ESS, L, resampled, max}, and ancestors if
-//          ESS < ess_frac * M (then logW = -log M).
-//  mode 1: input linear weights w; validates them; always resamples.
-// The CDF is over q_i = floor((w_i / max w) 2^K), K = 53 - ceil(log2 M): integer partial
-// sums below 2^53 are exact in FP64 in any order, so the scan is bit-exact.  Offspring i
-// sits at ((i + U) C) / M, product first (equal weights with U = 0 then map to the
-// identity for every M).
-__global__ __launch_bounds__(kRB) void lse_resample_kernel(LseArgs a) {
-  __shared__ double sh[kRB / 64];
-  __shared__ double tot[kRB];
-  const int M = a.M;
-  const int per = (M + kRB - 1) / kRB;
-  const int lo = min(M, threadIdx.x * per), hi = min(M, lo + per);
-  double *lw = a.logw;
-  int do_resample = 1;
-  if (a.mode == 0) {
-    double m = -INFINITY;
-    for (int i = lo; i < hi; ++i) m = fmax(m, lw[i]);
-    m = block_max(m, sh);
-    double s1 = 0.0;
-    for (int i = lo; i < hi; ++i) s1 += exp(lw[i] - m);
-    s1 = block_sum(s1, sh);
-    const double L = m + log(s1);
-    double s2 = 0.0;
-    for (int i = lo; i < hi; ++i) {
-      const double v = lw[i] - L;
-      lw[i] = v;
-      const double W = exp(v);
-      a.cdf[i] = W;   // kept for the resampling passes (same values, one exp per weight)
-      s2 += W * W;
+// Incremental weights, then the pieces of the normalisation and ESS (Section 4).
+//   logw_i <- logw_i + sum_j [log Gt(b_ij | a, lam_new) - log Gt(b_ij | a, lam_old)]
+//           = logw_i + p a log r - (a+1) sum_j log((a lam_new + |b_ij|)/(a lam_old + |b_ij|)),
+// r = lam_new/lam_old (a lane multiplies its at most 8 ratios, all in (r, 1], before one
+// log); the double exponential: p log(1/r) - (1/lam_new - 1/lam_old) sum_j |b_ij|.
+// With logw_{t-1} normalised, L = log sum_i exp(logw_i) is the log Z increment, and
+// ESS = (sum e^{logw})^2 / sum e^{2 logw}.  Each workgroup writes its maximum m_b and the
+// sums of e^{logw - m_b} and e^{2(logw - m_b)} (lse_finalize_kernel combines them).  The
+// log weights are left unnormalised (the next pass subtracts L).
+// The reweighting pass: one particle row per LP lanes, rw_rows(LP) = kBW / LP rows per
+// workgroup (larger workgroups, or several rows per lane with their loads issued together,
+// measured slower at n = 5000, p = 200, N = 16384).
+static __host__ __device__ constexpr int rw_rows(int LP) { return kBW / LP; }
+
+template <typename PT, int LP>
+__global__ __launch_bounds__(rw_rows(LP) * LP) void reweight_kernel(ReweightArgs a) {
+  constexpr int NP = 1;
+  constexpr int kRwRows = rw_rows(LP);
+  constexpr int WG = kRwRows * LP;
+  __shared__ double sh[WG / kWave];
+  const int lane = threadIdx.x & (LP - 1);
+  const int r0 = blockIdx.x * kRwRows + threadIdx.x / LP;
+  const int p = a.p;
+  const bool vec = (p & 3) == 0;
+  PT v[NP][2][4];
+  double lw0[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int i = r0 + q * kRwRows;
+    const bool live = i < a.M;
+    lw0[q] = live ? a.logw[i] : 0.0;
+    const PT *row = static_cast<const PT *>(a.beta) + (size_t)(live ? i : 0) * p;
+#pragma unroll
+    for (int kb = 0; kb < 2; ++kb) {
+      const int j0 = 4 * (lane + LP * kb);
+      if (live && j0 < p) load4(row, vec, j0, p, v[q][kb]);
+      else v[q][kb][0] = v[q][kb][1] = v[q][kb][2] = v[q][kb][3] = PT(0);
     }
-    s2 = block_sum(s2, sh);
-    const double ess = 1.0 / s2;
-    do_resample = ess < a.ess_frac * static_cast<double>(M);
-    if (threadIdx.x == 0) {
-      a.scalars[0] = ess;
-      a.scalars[1] = L;
-      a.scalars[2] = do_resample ? 1.0 : 0.0;
-      a.scalars[3] = m;
-      a.scalars[4] = (isfinite(L) && isfinite(ess)) ? 0.0 : 1.0;
-    }
-    if (!(isfinite(L) && isfinite(ess))) return;
-    if (!do_resample) return;
   }
-  // ---- weights and their maximum
-  const double *wsrc = a.w;   // mode 1 input
-  double wmax = -INFINITY;
-  int badw = 0;
-  for (int i = lo; i < hi; ++i) {
-    const double w = (a.mode == 0) ? a.cdf[i] : wsrc[i];
-    if (!(w >= 0.0) || isinf(w)) badw = 1;
-    wmax = fmax(wmax, w);
-  }
-  wmax = block_max(wmax, sh);
-  const double anybad = block_max(badw ? 1.0 : 0.0, sh);
-  if (anybad != 0.0 || !(wmax > 0.0)) {
-    if (threadIdx.x == 0) a.scalars[5] = 1.0;   // invalid weights: nothing written
-    return;
-  }
-  const double scale = ldexp(1.0, a.K);
-  // ---- local inclusive sums of the quantised weights, then an exclusive block scan
-  double run = 0.0;
-  for (int i = lo; i < hi; ++i) {
-    const double w = (a.mode == 0) ? a.cdf[i] : wsrc[i];
-    run += floor((w / wmax) * scale);
-    a.cdf[i] = run;
-  }
-  tot[threadIdx.x] = run;
-  __syncthreads();
-  for (int o = 1; o < kRB; o <<= 1) {    // Hillis-Steele inclusive scan of the totals
-    const double v = (threadIdx.x >= (unsigned)o) ? tot[threadIdx.x - o] : 0.0;
-    __syncthreads();
-    tot[threadIdx.x] += v;
-    __syncthreads();
-  }
-  const double base = (threadIdx.x > 0) ? tot[threadIdx.x - 1] : 0.0;
-  for (int i = lo; i < hi; ++i) a.cdf[i] += base;
-  __syncthreads();
-  __threadfence_block();
-  const double C = tot[kRB - 1];
-  // ---- offspring positions and binary search (no fused multiply-add)
-  const double U = static_cast<double>(a.u32) * 0x1p-32;
-  const double dM = static_cast<double>(M);
-  // The positions increase with i and a thread owns a contiguous block of offspring, so
-  // each search starts at the previous offspring's index and gallops forward (probes at
-  // distances 1, 2, 4, ...), then bisects the last interval: the same first index k with
-  // cdf[k] > t, in O(log distance) loads.
-  int k = 0;
-  for (int i = lo; i < hi; ++i) {
-    const double num = __dadd_rn(static_cast<double>(i), U);
-    const double tpos = __ddiv_rn(__dmul_rn(num, C), dM);
-    if (k < M && !(a.cdf[k] > tpos)) {
-      int below = k, above = M, step = 1;   // cdf[below] <= tpos; cdf[above] > tpos or above = M
-      while (below + step < M) {
-        if (a.cdf[below + step] > tpos) {
-          above = below + step;
-          break;
+  const double lr = log(a.lam_new / a.lam_old);
+  const double an = a.a * a.lam_new, ao = a.a * a.lam_old;
+  const double cst = static_cast<double>(p) * (a.a_inf ? -lr : a.a * lr);
+  double lw[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    double d;
+    if (a.a_inf) {
+      double sx = 0.0;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) sx += fabs(static_cast<double>(v[q][kb][e]));
+      d = -(1.0 / a.lam_new - 1.0 / a.lam_old) * sx;
+    } else {
+      // one division per lane: the products of the (at most 8) numerators and denominators;
+      // if either leaves the finite positive range, the product of the ratios instead
+      double num = 1.0, den = 1.0;
+#pragma unroll
+      for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const double x = fabs(static_cast<double>(v[q][kb][e]));
+          if (4 * (lane + LP * kb) + e < p) {
+            num *= an + x;
+            den *= ao + x;
+          }
         }
-        below += step;
-        step <<= 1;
+      double ratio = num / den;
+      if (!(num > 0.0 && num < INFINITY && den > 0.0 && den < INFINITY)) {
+        ratio = 1.0;
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double x = fabs(static_cast<double>(v[q][kb][e]));
+            if (4 * (lane + LP * kb) + e < p) ratio *= (an + x) / (ao + x);
+          }
       }
-      int l = below + 1, r = above;
-      while (l < r) {
-        const int mid = (l + r) >> 1;
-        if (a.cdf[mid] > tpos) r = mid;
-        else l = mid + 1;
-      }
-      k = l;
+      d = -(a.a + 1.0) * log(ratio);
     }
-    a.anc[i] = min(k, M - 1);
+    d = group_sum<LP>(d);
+    const int i = r0 + q * kRwRows;
+    lw[q] = -INFINITY;   // rows past M carry no weight
+    if (i < a.M) {
+      lw[q] = lw0[q] + d + cst;
+      if (lane == 0) a.logw[i] = lw[q];
+    }
   }
-  if (a.mode == 0) {
-    const double lN = -log(dM);
-    for (int i = lo; i < hi; ++i) lw[i] = lN;
+  double m = lw[0];
+#pragma unroll
+  for (int q = 1; q < NP; ++q) m = fmax(m, lw[q]);
+  m = wg_max<WG>(m, sh);
+  double e1 = 0.0, e2 = 0.0;
+  if (lane == 0 && m != -INFINITY)
+#pragma unroll
+    for (int q = 0; q < NP; ++q)
+      if (r0 + q * kRwRows < a.M) {
+        const double e = exp(lw[q] - m);
+        e1 += e;
+        e2 += e * e;
+      }
+  const double s1 = wg_sum<WG>(e1, sh);
+  const double s2 = wg_sum<WG>(e2, sh);
+  if (threadIdx.x == 0) {
+    double *o = a.part + 3 * (size_t)blockIdx.x;
+    o[0] = m;
+    o[1] = s1;
+    o[2] = s2;
   }
-  if (threadIdx.x == 0) a.scalars[5] = 0.0;
 }
 
-template <typename PT>
-__global__ void gather_kernel(const int *__restrict__ anc, int M, int p, const PT *__restrict__ src,
-                              PT *__restrict__ dst, const PT *__restrict__ gsrc, PT *__restrict__ gdst,
-                              const double *__restrict__ llsrc, double *__restrict__ lldst) {
-  const int lane = threadIdx.x & 63;
-  const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (i >= M) return;
-  const size_t k = static_cast<size_t>(anc[i]);
-  for (int j = lane; j < p; j += 64) {
-    dst[(size_t)i * p + j] = src[k * p + j];
-    if (gsrc) gdst[(size_t)i * p + j] = gsrc[k * p + j];
+// Combination of the reweighting pass's G workgroup partials in workgroup order (one
+// workgroup; the kernel boundary makes the partials visible):
+//   L = m + log S1, ESS = S1^2 / S2, S1 = sum_b e^{m_b - m} s1_b, S2 = sum_b e^{2(m_b - m)} s2_b,
+// m = max_b m_b; writes {ESS, L, resample flag, m, non-finite flag, 0} to scalars.
+constexpr int kFin = 1024;   // threads of the combination kernel
+
+__global__ __launch_bounds__(kFin) void lse_finalize_kernel(const double *__restrict__ part, int G, int M,
+                                                            double ess_frac, double *__restrict__ scalars) {
+  __shared__ double sh[kFin / kWave];
+  constexpr int B = 4;   // partials per thread per batch, their loads issued together
+  double gm = -INFINITY, t1 = 0.0, t2 = 0.0;
+  // the batches run in order; within one, thread t holds partials b0 + t + kBW u
+  double mb[B], p1[B], p2[B];
+  for (int b0 = 0; b0 < G; b0 += B * kFin) {
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int b = b0 + threadIdx.x + u * kFin;
+      mb[u] = b < G ? part[3 * (size_t)b] : -INFINITY;
+      p1[u] = b < G ? part[3 * (size_t)b + 1] : 0.0;
+      p2[u] = b < G ? part[3 * (size_t)b + 2] : 0.0;
+    }
+    double bm = mb[0];
+#pragma unroll
+    for (int u = 1; u < B; ++u) bm = fmax(bm, mb[u]);
+    bm = wg_max<kFin>(bm, sh);
+    const double nm = fmax(gm, bm);   // running maximum; earlier sums rescaled to it
+    if (nm != -INFINITY) {
+      if (gm != -INFINITY && nm != gm) {
+        const double f = exp(gm - nm);
+        t1 *= f;
+        t2 *= f * f;
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u)
+        if (mb[u] != -INFINITY) {
+          const double f = exp(mb[u] - nm);
+          t1 += p1[u] * f;
+          t2 += p2[u] * (f * f);
+        }
+    }
+    gm = nm;
   }
-  if (lane == 0) lldst[i] = llsrc[k];
+  t1 = wg_sum<kFin>(t1, sh);
+  t2 = wg_sum<kFin>(t2, sh);
+  if (threadIdx.x == 0) {
+    const double L = gm + log(t1);
+    const double ess = t1 * t1 / t2;
+    const bool ok = isfinite(L) && isfinite(ess);
+    scalars[0] = ess;
+    scalars[1] = L;
+    scalars[2] = (ok && ess < ess_frac * static_cast<double>(M)) ? 1.0 : 0.0;
+    scalars[3] = gm;
+    scalars[4] = ok ? 0.0 : 1.0;
+    scalars[5] = 0.0;   // no invalid-weight flag for the resampling passes that may follow
+  }
+}
+
+// ---------------------------------------------------------------- systematic resampling
+// On the quantised weights q_i = floor(x_i 2^K), K = 53 - ceil(log2 M), x_i in [0, 1] the
+// weight relative to the largest: every partial sum C_k = q_0 + ... + q_k is an integer
+// below 2^53, exact in FP64 in any summation order, so the multi-workgroup scan below is
+// bit-exact.  Offspring i takes the first k with C_k > ((i + U) C) / M (the product first,
+// no fused multiply-add), clamped to M - 1, C = C_{M-1}.
+
+// Validation and maximum of linear weights (spa_smc_resample), per workgroup:
+// part[2b] = max w, part[2b+1] = 1 if a weight is negative, NaN or infinite.
+__global__ __launch_bounds__(kBW) void wmax_kernel(const double *__restrict__ w, int M, double *__restrict__ part) {
+  __shared__ double sh[kBW / kWave];
+  double m = -INFINITY, bad = 0.0;
+  for (int i = blockIdx.x * kBW + threadIdx.x; i < M; i += gridDim.x * kBW) {
+    const double v = w[i];
+    if (!(v >= 0.0) || isinf(v)) bad = 1.0;
+    m = fmax(m, v);
+  }
+  m = wg_max(m, sh);
+  bad = wg_max(bad, sh);
+  if (threadIdx.x == 0) {
+    part[2 * (size_t)blockIdx.x] = m;
+    part[2 * (size_t)blockIdx.x + 1] = bad;
+  }
+}
+
+// q_i into cdf[i] and the sum of q over each workgroup's range of kBW * ept weights (ept
+// per thread, coalesced).  mode 0: x_i = min(e^{logw_i - max logw}, 1) from the
+// reweighting pass's unnormalised log weights (scalars[3] = their maximum); mode 1:
+// x_i = w_i / max w, max w and validity from the G workgroup partials of wmax_kernel
+// (workgroup 0 records them: scalars[6] = max w, scalars[5] = 1 for invalid weights, all
+// zero included, and then nothing is quantised).
+__global__ __launch_bounds__(kBW) void quantise_kernel(int mode, const double *__restrict__ logw,
+                                                       const double *__restrict__ w, const double *__restrict__ wpart,
+                                                       int M, int K, int ept, double *__restrict__ scalars,
+                                                       double *__restrict__ cdf, double *__restrict__ btot) {
+  __shared__ double sh[kBW / kWave];
+  double ref;
+  if (mode == 0) {
+    ref = scalars[3];
+  } else {
+    double m = -INFINITY, bad = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBW) {
+      m = fmax(m, wpart[2 * (size_t)b]);
+      bad = fmax(bad, wpart[2 * (size_t)b + 1]);
+    }
+    m = wg_max(m, sh);
+    bad = wg_max(bad, sh);
+    const bool invalid = bad != 0.0 || !(m > 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      scalars[5] = invalid ? 1.0 : 0.0;
+      scalars[6] = m;
+    }
+    if (invalid) return;
+    ref = m;
+  }
+  const double scale = ldexp(1.0, K);
+  const size_t base = (size_t)blockIdx.x * kBW * ept;
+  double s = 0.0;
+  for (int e = 0; e < ept; ++e) {
+    const size_t i = base + (size_t)e * kBW + threadIdx.x;
+    if (i < (size_t)M) {
+      const double x = mode == 0 ? fmin(exp(logw[i] - ref), 1.0) : w[i] / ref;
+      const double q = floor(x * scale);
+      cdf[i] = q;
+      s += q;
+    }
+  }
+  s = wg_sum(s, sh);
+  if (threadIdx.x == 0) btot[blockIdx.x] = s;
+}
+
+// Inclusive scan of q over the whole array: a workgroup adds the totals of the ranges
+// before its own, then scans its range (ept consecutive values per thread, a wave scan of
+// the thread totals, the wave totals in order).  scalars[7] = C.
+__global__ __launch_bounds__(kBW) void cdf_scan_kernel(int M, int ept, const double *__restrict__ btot,
+                                                       double *__restrict__ cdf, double *__restrict__ scalars) {
+  __shared__ double sh[kBW / kWave];
+  __shared__ double wtot[kBW / kWave];
+  if (scalars[5] != 0.0) return;
+  const int G = gridDim.x;
+  double before = 0.0, all = 0.0;
+  for (int b = threadIdx.x; b < G; b += kBW) {
+    const double v = btot[b];
+    all += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  before = wg_sum(before, sh);
+  all = wg_sum(all, sh);
+  const size_t lo = (size_t)blockIdx.x * kBW * ept + (size_t)threadIdx.x * ept;
+  double run = 0.0;
+  for (int e = 0; e < ept; ++e)
+    if (lo + e < (size_t)M) run += cdf[lo + e];
+  // inclusive wave scan of the thread totals
+  const int ln = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  double inc = run;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const double v = __shfl_up(inc, o, kWave);
+    if (ln >= o) inc += v;
+  }
+  if (ln == kWave - 1) wtot[wv] = inc;
+  __syncthreads();
+  double off = before;
+  for (int q = 0; q < wv; ++q) off += wtot[q];
+  off += inc - run;   // exclusive prefix of this thread
+  for (int e = 0; e < ept; ++e)
+    if (lo + e < (size_t)M) {
+      off += cdf[lo + e];
+      cdf[lo + e] = off;
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) scalars[7] = all;
+}
+
+// Offspring search, LP lanes per offspring: each round the lanes probe the ends of LP
+// equal segments of the remaining range [lo, hi] (hi = M or a position whose C exceeds
+// the target) and keep the first segment whose end exceeds it, so M = 16384 takes three
+// rounds of loads at LP = 32.  Optionally the offspring's rows are gathered from its
+// ancestor (particles, gradients, log-likelihoods) and its log weight set to -log M.
+template <typename PT, int LP>
+__global__ __launch_bounds__(kBW) void search_gather_kernel(ResampleArgs a) {
+  if (a.scalars[5] != 0.0) return;
+  const int lane = threadIdx.x & (LP - 1);
+  const int i = blockIdx.x * (kBW / LP) + threadIdx.x / LP;
+  if (i >= a.M) return;   // whole groups leave together
+  const double C = a.scalars[7];
+  const double U = static_cast<double>(a.u32) * 0x1p-32;
+  const double tpos = __ddiv_rn(__dmul_rn(__dadd_rn(static_cast<double>(i), U), C), static_cast<double>(a.M));
+  const int gbase = (threadIdx.x & (kWave - 1)) & ~(LP - 1);   // first lane of the group in the wave
+  int lo = 0, hi = a.M;
+  while (lo < hi) {
+    const int step = (hi - lo + LP - 1) / LP;
+    const int pos = lo + (lane + 1) * step - 1;
+    const bool gt = pos >= hi || a.cdf[pos] > tpos;
+    const unsigned long long bal = __ballot(gt);
+    const unsigned long long gm = (bal >> gbase) & (LP == 64 ? ~0ull : ((1ull << LP) - 1));
+    if (gm == 0ull) {   // even C at hi - 1 does not exceed the target: the answer is hi
+      lo = hi;
+      break;
+    }
+    const int f = __builtin_ctzll(gm);   // first segment whose end exceeds the target
+    const int flo = lo + f * step;
+    const int fhi = min(lo + (f + 1) * step - 1, hi);
+    lo = flo;
+    hi = fhi;
+    if (fhi == flo) break;
+  }
+  const int k = min(lo, a.M - 1);
+  if (lane == 0) a.anc[i] = k;
+  if (!a.src) return;
+  const int p = a.p;
+  const bool vec = (p & 3) == 0;
+  const PT *s = static_cast<const PT *>(a.src) + (size_t)k * p;
+  PT *d = static_cast<PT *>(a.dst) + (size_t)i * p;
+  const PT *gs = a.gsrc ? static_cast<const PT *>(a.gsrc) + (size_t)k * p : nullptr;
+  PT *gd = a.gsrc ? static_cast<PT *>(a.gdst) + (size_t)i * p : nullptr;
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) {
+    const int j0 = 4 * (lane + LP * kb);
+    if (j0 < p) {
+      PT v[4];
+      load4(s, vec, j0, p, v);
+      store4(d, vec, j0, p, v);
+      if (gs) {
+        load4(gs, vec, j0, p, v);
+        store4(gd, vec, j0, p, v);
+      }
+    }
+  }
+  if (lane == 0) {
+    a.lldst[i] = a.llsrc[k];
+    a.logw[i] = a.logw_eq;
+  }
 }
 
 // ---- weighted moments per coefficient (two kernels: chunk partials, ordered combine).
 // Partial sums are shifted by the first particle's row (removes cancellation):
 //   S0 = sum W, S1_j = sum W (b_ij - c_j), S2_j = sum W (b_ij - c_j)^2.
-// A workgroup covers 64 columns and one chunk of at most 256 rows; W_i = exp(logw_i) is
-// evaluated once per row into LDS.
+// A workgroup covers one chunk of kMomRows rows and every column: RG row groups of CP
+// column threads (CP = p rounded up to 64, at most 256; RG = 256 / CP), whose partials are
+// added in row-group order.  With `shift`, the chunk's log weights are first normalised
+// in place (logw_i -= *shift); only this workgroup reads those rows' weights.
+constexpr int kMomRows = 64;
+
 template <typename PT>
-__global__ void moments_partial_kernel(const PT *__restrict__ beta, const double *__restrict__ logw,
-                                       int M, int p, int rows_per_chunk, double *__restrict__ part) {
-  __shared__ double Wsh[256];
-  __shared__ double sh[3][4][64];
-  const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int rg = threadIdx.x >> 6;   // 4 row groups
-  const int chunk = blockIdx.y;
-  const int r0 = chunk * rows_per_chunk, r1 = min(M, r0 + rows_per_chunk);
-  if (r0 + (int)threadIdx.x < r1) Wsh[threadIdx.x] = exp(logw[r0 + threadIdx.x]);
-  __syncthreads();
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  const double c = (col < p) ? static_cast<double>(beta[col]) : 0.0;
-  for (int i = r0 + rg; i < r1; i += 4) {
-    const double W = Wsh[i - r0];
-    s0 += W;
-    if (col < p) {
-      const double dd = static_cast<double>(beta[(size_t)i * p + col]) - c;
-      s1 += W * dd;
-      s2 += W * dd * dd;
+__global__ __launch_bounds__(kBW) void moments_partial_kernel(const PT *__restrict__ beta, double *__restrict__ logw,
+                                                              const double *__restrict__ shift, int M, int p,
+                                                              double *__restrict__ part) {
+  __shared__ double Wsh[kMomRows];
+  __shared__ double sh[3][kBW];
+  const int chunk = blockIdx.x;
+  const int r0 = chunk * kMomRows, r1 = min(M, r0 + kMomRows);
+  if ((int)threadIdx.x < r1 - r0) {
+    double lw = logw[r0 + threadIdx.x];
+    if (shift) {
+      lw -= *shift;
+      logw[r0 + threadIdx.x] = lw;
     }
+    Wsh[threadIdx.x] = exp(lw);
   }
-  sh[0][rg][threadIdx.x & 63] = s0;
-  sh[1][rg][threadIdx.x & 63] = s1;
-  sh[2][rg][threadIdx.x & 63] = s2;
   __syncthreads();
-  if (rg == 0 && col < p) {
-    const int l = threadIdx.x & 63;
-    double t0 = sh[0][0][l], t1 = sh[1][0][l], t2 = sh[2][0][l];
-    for (int q = 1; q < 4; ++q) {
-      t0 += sh[0][q][l];
-      t1 += sh[1][q][l];
-      t2 += sh[2][q][l];
+  const int CP = min(kBW, (p + 63) / 64 * 64);
+  const int RG = kBW / CP;
+  const int rg = threadIdx.x / CP, cl = threadIdx.x % CP;
+  for (int col0 = 0; col0 < p; col0 += CP) {   // one pass unless p > 256
+    const int col = col0 + cl;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (rg < RG && col < p) {
+      const double c = static_cast<double>(beta[col]);
+      const PT *bp = beta + col;
+      int i = r0 + rg;
+      for (; i + 15 * RG < r1; i += 16 * RG) {   // sixteen rows' loads in flight, then in order
+        PT v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = bp[(size_t)(i + u * RG) * p];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const double W = Wsh[i + u * RG - r0];
+          const double dd = static_cast<double>(v[u]) - c;
+          s0 += W;
+          s1 += W * dd;
+          s2 += W * dd * dd;
+        }
+      }
+      for (; i < r1; i += RG) {
+        const double W = Wsh[i - r0];
+        const double dd = static_cast<double>(bp[(size_t)i * p]) - c;
+        s0 += W;
+        s1 += W * dd;
+        s2 += W * dd * dd;
+      }
     }
-    double *o = part + ((size_t)chunk * p + col) * 3;
-    o[0] = t0;
-    o[1] = t1;
-    o[2] = t2;
+    if (RG > 1) {
+      __syncthreads();
+      sh[0][threadIdx.x] = s0;
+      sh[1][threadIdx.x] = s1;
+      sh[2][threadIdx.x] = s2;
+      __syncthreads();
+      if (rg == 0)
+        for (int q = 1; q < RG; ++q) {
+          s0 += sh[0][q * CP + cl];
+          s1 += sh[1][q * CP + cl];
+          s2 += sh[2][q * CP + cl];
+        }
+    }
+    if (rg == 0 && col < p) {
+      double *o = part + ((size_t)chunk * p + col) * 3;
+      o[0] = s0;
+      o[1] = s1;
+      o[2] = s2;
+    }
   }
 }
 
@@ -1065,48 +1279,67 @@ void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const Prop
   else launch_accept_p<Prec::BF16X2, float>(mala, parts, PP, a, next, st);   // no operand written: one instance
 }
 
-void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,
-                     double lam_old, double *logw, hipStream_t st) {
-  const int grid = grid_rows(M, 4);
-  if (f64)
-    hipLaunchKernelGGL(reweight_kernel<double>, dim3(grid), dim3(256), 0, st, (const double *)beta, M, p, a,
-                       a_inf, lam_new, lam_old, logw);
-  else
-    hipLaunchKernelGGL(reweight_kernel<float>, dim3(grid), dim3(256), 0, st, (const float *)beta, M, p, a,
-                       a_inf, lam_new, lam_old, logw);
+int reweight_blocks(int M, int p) {
+  const int rows = rw_rows(bw_lanes(p));
+  return std::max(1, (M + rows - 1) / rows);
 }
 
-void launch_lse_resample(const LseArgs &a, hipStream_t st) {
-  hipLaunchKernelGGL(lse_resample_kernel, dim3(1), dim3(kRB), 0, st, a);
+template <int LP>
+static void launch_reweight_lp(bool f64, const ReweightArgs &a, hipStream_t st) {
+  const dim3 grid(reweight_blocks(a.M, a.p));
+  const dim3 block(rw_rows(LP) * LP);
+  if (f64) hipLaunchKernelGGL((reweight_kernel<double, LP>), grid, block, 0, st, a);
+  else hipLaunchKernelGGL((reweight_kernel<float, LP>), grid, block, 0, st, a);
 }
 
-void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void *dst, const void *gsrc,
-                   void *gdst, const double *llsrc, double *lldst, hipStream_t st) {
-  const int grid = grid_rows(M, 4);
-  if (f64)
-    hipLaunchKernelGGL(gather_kernel<double>, dim3(grid), dim3(256), 0, st, anc, M, p, (const double *)src,
-                       (double *)dst, (const double *)gsrc, (double *)gdst, llsrc, lldst);
-  else
-    hipLaunchKernelGGL(gather_kernel<float>, dim3(grid), dim3(256), 0, st, anc, M, p, (const float *)src,
-                       (float *)dst, (const float *)gsrc, (float *)gdst, llsrc, lldst);
+void launch_reweight(bool f64, const ReweightArgs &a, hipStream_t st) {
+  switch (bw_lanes(a.p)) {
+    case 8: launch_reweight_lp<8>(f64, a, st); break;
+    case 16: launch_reweight_lp<16>(f64, a, st); break;
+    case 32: launch_reweight_lp<32>(f64, a, st); break;
+    default: launch_reweight_lp<64>(f64, a, st); break;
+  }
+  hipLaunchKernelGGL(lse_finalize_kernel, dim3(1), dim3(kFin), 0, st, a.part, reweight_blocks(a.M, a.p), a.M,
+                     a.ess_frac, a.scalars);
 }
 
-// 64-row chunks: 4 row groups of 16 rows per workgroup (N/64 x p/64 workgroups)
-int moments_chunks(int M) { return std::max(1, (M + 63) / 64); }
+template <int LP>
+static void launch_search_lp(bool f64, const ResampleArgs &a, hipStream_t st) {
+  const dim3 grid((a.M + kBW / LP - 1) / (kBW / LP));
+  if (f64) hipLaunchKernelGGL((search_gather_kernel<double, LP>), grid, dim3(kBW), 0, st, a);
+  else hipLaunchKernelGGL((search_gather_kernel<float, LP>), grid, dim3(kBW), 0, st, a);
+}
 
-void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
+void launch_resample(bool f64, const ResampleArgs &a, hipStream_t st) {
+  // ept weights per thread so that a pass has at most kResampleBlocks workgroups
+  const int ept = std::max(1, (a.M + kBW * kResampleBlocks - 1) / (kBW * kResampleBlocks));
+  const int G = (a.M + kBW * ept - 1) / (kBW * ept);
+  if (a.mode == 1) hipLaunchKernelGGL(wmax_kernel, dim3(G), dim3(kBW), 0, st, a.w, a.M, a.wpart);
+  hipLaunchKernelGGL(quantise_kernel, dim3(G), dim3(kBW), 0, st, a.mode, a.logw, a.w, a.wpart, a.M, a.K, ept,
+                     a.scalars, a.cdf, a.btot);
+  hipLaunchKernelGGL(cdf_scan_kernel, dim3(G), dim3(kBW), 0, st, a.M, ept, a.btot, a.cdf, a.scalars);
+  switch (a.src ? bw_lanes(a.p) : 32) {
+    case 8: launch_search_lp<8>(f64, a, st); break;
+    case 16: launch_search_lp<16>(f64, a, st); break;
+    case 32: launch_search_lp<32>(f64, a, st); break;
+    default: launch_search_lp<64>(f64, a, st); break;
+  }
+}
+
+// 64-row chunks, every column in one workgroup
+int moments_chunks(int M) { return std::max(1, (M + kMomRows - 1) / kMomRows); }
+
+void launch_moments(bool f64, const void *beta, double *logw, const double *shift, int M, int p, double *part,
                     double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st) {
   const int nch = moments_chunks(M);
-  const int rpc = (M + nch - 1) / nch;
-  dim3 grid((p + 63) / 64, nch);
   if (f64) {
-    hipLaunchKernelGGL(moments_partial_kernel<double>, grid, dim3(256), 0, st, (const double *)beta, logw, M, p,
-                       rpc, part);
+    hipLaunchKernelGGL(moments_partial_kernel<double>, dim3(nch), dim3(kBW), 0, st, (const double *)beta, logw,
+                       shift, M, p, part);
     hipLaunchKernelGGL(moments_final_kernel<double>, dim3((p + 3) / 4), dim3(256), 0, st,
                        (const double *)beta, part, nch, p, mean, var, sigma, sigma_floor);
   } else {
-    hipLaunchKernelGGL(moments_partial_kernel<float>, grid, dim3(256), 0, st, (const float *)beta, logw, M, p,
-                       rpc, part);
+    hipLaunchKernelGGL(moments_partial_kernel<float>, dim3(nch), dim3(kBW), 0, st, (const float *)beta, logw,
+                       shift, M, p, part);
     hipLaunchKernelGGL(moments_final_kernel<float>, dim3((p + 3) / 4), dim3(256), 0, st,
                        (const float *)beta, part, nch, p, mean, var, sigma, sigma_floor);
   }

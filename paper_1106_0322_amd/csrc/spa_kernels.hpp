@@ -59,16 +59,39 @@ struct AcceptArgs {
   int t;
 };
 
-struct LseArgs {
-  int mode;              // 0: log weights (normalise, ESS, maybe resample); 1: linear weights
-  int M, K;
-  double ess_frac;
-  double *logw;          // mode 0: in/out
-  const double *w;       // mode 1: input weights
-  double *cdf;           // M scratch
-  int *anc;              // M output ancestors
-  double *scalars;       // {ess, log Z increment, resampled, max, nonfinite, invalid weights}
-  uint32_t u32;
+// Incremental weights with the normalisation and ESS partials (reweight_kernel).
+struct ReweightArgs {
+  const void *beta;            // M x p particles (FP64 or FP32)
+  int M, p;
+  double a;                    // Gt degrees of freedom (unused when a_inf)
+  int a_inf;
+  double lam_new, lam_old, ess_frac;
+  double *logw;                // in: normalised log W_{t-1}; out: unnormalised log weights
+  double *part;                // 3 x reweight_blocks(M, p) workgroup partials
+  double *scalars;             // out: {ESS, L, resample flag, max log weight, non-finite, 0}
+};
+
+// Systematic resampling on the exact quantised CDF (quantise, scan, search [+ gather]).
+struct ResampleArgs {
+  int mode;                    // 0: from the reweighting pass's log weights; 1: linear weights w
+  int M, K;                    // K = 53 - ceil(log2 M)
+  uint32_t u32;                // offset U = u32 2^-32
+  double *logw;                // mode 0: unnormalised log weights in; set to logw_eq when gathering
+  double logw_eq;              // -log M
+  const double *w;             // mode 1: weights >= 0
+  double *cdf;                 // M scratch
+  double *btot;                // 1024 scratch
+  double *wpart;               // 2 x 1024 scratch (mode 1)
+  double *scalars;             // [3] max log weight (mode 0), [5] invalid flag, [6] max w, [7] C
+  int *anc;                    // M ancestors (out)
+  // gather (null src: ancestors only): particle rows, gradient rows (nullable), loglik
+  int p;
+  const void *src;
+  void *dst;
+  const void *gsrc;
+  void *gdst;
+  const double *llsrc;
+  double *lldst;
 };
 
 void launch_col_stats(const uint8_t *X, const uint8_t *y, int n, int p, double *mu, double *s,
@@ -84,13 +107,16 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st);
 // a launch_propose with *next) from each row it has just decided.  PP: the padded row
 // length of the contraction's operand (it sets the lanes per particle row).
 void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st);
-void launch_reweight(bool f64, const void *beta, int M, int p, double a, int a_inf, double lam_new,
-                     double lam_old, double *logw, hipStream_t st);
-void launch_lse_resample(const LseArgs &a, hipStream_t st);
-void launch_gather(bool f64, const int *anc, int M, int p, const void *src, void *dst, const void *gsrc,
-                   void *gdst, const double *llsrc, double *lldst, hipStream_t st);
+// Workgroups of the reweighting pass (its partials hold 3 doubles per workgroup); the
+// launch is the pass and the one-workgroup combination of its partials.
+int reweight_blocks(int M, int p);
+void launch_reweight(bool f64, const ReweightArgs &a, hipStream_t st);
+// Scratch of the resampling passes: at most this many workgroups per pass.
+constexpr int kResampleBlocks = 1024;
+void launch_resample(bool f64, const ResampleArgs &a, hipStream_t st);
 int moments_chunks(int M);
-void launch_moments(bool f64, const void *beta, const double *logw, int M, int p, double *part,
+// shift (nullable, device): the log weights are first normalised in place, logw -= *shift.
+void launch_moments(bool f64, const void *beta, double *logw, const double *shift, int M, int p, double *part,
                     double *mean, double *var, double *sigma, double sigma_floor, hipStream_t st);
 // out[0] = sum of the accept counts; out[1] = particles with a non-finite log-likelihood
 // (ll may be null: 0).

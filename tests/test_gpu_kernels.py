@@ -235,7 +235,9 @@ def test_autograd_function_backward_is_the_adjoint():
     assert np.allclose(b.grad.cpu().numpy(), w.cpu().numpy()[:, None] * g_ref, rtol=1e-9, atol=1e-9)
 
 
-@pytest.mark.parametrize("M", [1, 2, 7, 64, 1000, 1024, 4097, 16384, 32768, 100000])
+# M spans one workgroup, ragged multi-workgroup ranges, and (M > 2^18) several weights per
+# thread in the quantisation and scan passes
+@pytest.mark.parametrize("M", [1, 2, 7, 64, 255, 257, 1000, 1024, 4097, 16384, 32768, 100000, 1000003])
 def test_resample_bit_exact(M):
     torch = _torch()
     s, *_ = _sampler("n500_p10_rwm_fp64", "fp64")

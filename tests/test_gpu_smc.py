@@ -70,6 +70,98 @@ def test_one_step_weights_and_resampling_fp64(t):
     assert np.allclose(var[t], v_ref, rtol=1e-9, atol=1e-15)
 
 
+@pytest.mark.parametrize("name", ["n5000_p200_mala_bf16", "n10000_p500_mala_fp8", "n2000_p50_rwm_fp32"])
+def test_one_step_weights_and_resampling_full_size(name):
+    """The reweighting pass (multi-workgroup logsumexp/ESS partials, combined by the last
+    workgroup) and the resampling passes (quantised CDF scan, offspring search and gather)
+    at the workloads' particle counts and row lengths, from a given state whose weights
+    force resampling: ESS and log Z increment to 1e-11, ancestors through the gathered
+    rows bit for bit, equal weights afterwards, the moments of the gathered cloud."""
+    torch = _torch()
+    cfg, X, y, Xs = dataset(name)
+    rng = np.random.default_rng(5)
+    N, p = cfg.N, X.shape[1]
+    beta = np.clip(rng.normal(0.0, 0.1, size=(N, p)), -2, 2).astype(np.float32)
+    beta[rng.uniform(size=(N, p)) < 0.2] = 0.0
+    logw = rng.normal(0.0, 2.0, size=N)
+    logw -= smc.logsumexp(logw)
+    t = 40
+    g = _gpu(cfg, X, y, sweeps=0, init_sweeps=0)
+    g.set_state(torch.from_numpy(beta), torch.from_numpy(logw), t, 0.1)
+    out = g.step()
+    lam = cfg.grid()
+    b64 = beta.astype(np.float64)
+    lw, L = smc.normalise(logw + smc.reweight_delta(b64, cfg.a, lam[t], lam[t - 1]))
+    e = smc.ess(lw)
+    assert e < cfg.ess_frac * N and out["resampled"]
+    assert abs(out["ess"] - e) <= 1e-11 * e
+    assert abs(out["log_z_inc"] - L) <= 1e-11 * max(1.0, abs(L))
+    anc = smc.systematic_resample(np.exp(lw), philox.resample_u32(cfg.seed, t + 1))
+    gb, glw = g.particles()
+    assert np.array_equal(gb.cpu().numpy(), beta[anc])
+    assert np.all(glw.cpu().numpy() == -math.log(N))
+    mean, var, _ = g.paths()
+    m_ref, v_ref = smc.weighted_moments(b64[anc], np.full(N, -math.log(N)))
+    assert np.allclose(mean[t], m_ref, rtol=1e-10, atol=1e-13)
+    assert np.allclose(var[t], v_ref, rtol=1e-9, atol=1e-15)
+    g.close()
+
+
+def test_reweight_extreme_coefficients_fp64():
+    """Coefficients so large that a lane's product of prior-factor numerators overflows
+    (the pass then multiplies the ratios one by one), and exact zeros: the increments match
+    the oracle's log1p form to 1e-11."""
+    torch = _torch()
+    cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
+    rng = np.random.default_rng(9)
+    N = 512
+    beta = rng.normal(0.0, 0.3, size=(N, cfg.p))
+    beta[::7] *= 1e80
+    beta[3::11] = 0.0
+    logw = np.full(N, -math.log(N))
+    t = 12
+    g = _gpu(cfg, X, y, N=N, sweeps=0, init_sweeps=0, ess_frac=1e-9)
+    g.set_state(torch.from_numpy(beta), torch.from_numpy(logw), t, 0.1)
+    out = g.step()
+    lam = cfg.grid()
+    delta = smc.reweight_delta(beta, cfg.a, lam[t], lam[t - 1])
+    lw, L = smc.normalise(logw + delta)
+    assert not out["resampled"]
+    assert abs(out["log_z_inc"] - L) <= 1e-11 * max(1.0, abs(L))
+    assert abs(out["ess"] - smc.ess(lw)) <= 1e-11 * smc.ess(lw)
+    glw = g.particles()[1].cpu().numpy()
+    assert np.allclose(glw, lw, rtol=1e-12, atol=1e-11)
+    g.close()
+
+
+def test_one_step_weights_without_resampling_full_size():
+    """No resampling: the moment pass normalises the log weights by L in place."""
+    torch = _torch()
+    cfg, X, y, Xs = dataset("n5000_p200_mala_bf16")
+    rng = np.random.default_rng(6)
+    N, p = cfg.N, X.shape[1]
+    beta = np.clip(rng.normal(0.0, 0.1, size=(N, p)), -2, 2).astype(np.float32)
+    logw = rng.normal(0.0, 0.1, size=N)
+    logw -= smc.logsumexp(logw)
+    t = 60
+    g = _gpu(cfg, X, y, sweeps=0, init_sweeps=0)
+    g.set_state(torch.from_numpy(beta), torch.from_numpy(logw), t, 0.1)
+    out = g.step()
+    lam = cfg.grid()
+    b64 = beta.astype(np.float64)
+    lw, L = smc.normalise(logw + smc.reweight_delta(b64, cfg.a, lam[t], lam[t - 1]))
+    assert not out["resampled"]
+    assert abs(out["log_z_inc"] - L) <= 1e-11 * max(1.0, abs(L))
+    gb, glw = g.particles()
+    assert np.array_equal(gb.cpu().numpy(), beta)
+    assert np.allclose(glw.cpu().numpy(), lw, rtol=0, atol=1e-11)
+    mean, var, _ = g.paths()
+    m_ref, v_ref = smc.weighted_moments(b64, lw)
+    assert np.allclose(mean[t], m_ref, rtol=1e-10, atol=1e-13)
+    assert np.allclose(var[t], v_ref, rtol=1e-9, atol=1e-15)
+    g.close()
+
+
 def test_one_step_with_moves_fp64():
     torch = _torch()
     cfg, X, y, Xs = dataset("n500_p10_rwm_fp64")
