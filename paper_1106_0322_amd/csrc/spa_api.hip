@@ -1107,12 +1107,17 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
     for (int s = 0; s < h->sweeps; ++s)
       if ((st = sweep(h, t_new, s, lam_new, s > 0, s + 1 < h->sweeps)) != SPA_OK) return st;
   }
-  long long cnt = 0, bad_ll = 0;
-  if ((st = read_count(h, &cnt, &bad_ll)) != SPA_OK) return st;
-  if (bad_ll) return set_err(h, SPA_ERR_NUMERIC, std::to_string(bad_ll) + " particle(s) with a non-finite log-likelihood");
+  // accept count and non-finite log-likelihoods, read back with the step's one final
+  // synchronisation (after the per-scale records are enqueued)
+  launch_count(h->acc, h->N, h->ll, h->dcount, h->stream);
+  SPA_CK(h, hipMemcpyAsync(h->hcount, h->dcount, 2 * sizeof(long long), hipMemcpyDeviceToHost, h->stream));
   if ((st = record_moments(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_summaries(h, t_new - 1)) != SPA_OK) return st;
   if ((st = record_map(h, t_new - 1)) != SPA_OK) return st;
+  SPA_CK(h, hipStreamSynchronize(h->stream));
+  tflush(h);
+  const long long cnt = h->hcount[0], bad_ll = h->hcount[1];
+  if (bad_ll) return set_err(h, SPA_ERR_NUMERIC, std::to_string(bad_ll) + " particle(s) with a non-finite log-likelihood");
   const double upd = static_cast<double>(h->N) * (h->move == SPA_MOVE_SINGLE ? h->p : 1);   // MH decisions per sweep
   const double acc_rate = h->sweeps > 0 ? static_cast<double>(cnt) / (upd * h->sweeps) : NAN;
   if (h->sweeps > 0) adapt_step(h, acc_rate);
@@ -1130,8 +1135,6 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   s.step = step_used;
   h->stats.push_back(s);
   if (out) *out = s;
-  SPA_CK(h, hipStreamSynchronize(h->stream));
-  tflush(h);
   return SPA_OK;
 }
 

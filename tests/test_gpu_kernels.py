@@ -74,6 +74,25 @@ def test_loglik_fp8_storage_equals_bf16_storage(n, p):
     assert torch.equal(s8.loglik(b), s16.loglik(b))
 
 
+@pytest.mark.parametrize("n,p,M", [(2000, 50, 257), (5000, 200, 1000), (334, 127, 130), (1000, 255, 64),
+                                   (130, 63, 129), (64, 100, 200)])
+def test_grad_fp8_storage_equals_bf16_storage(n, p, M):
+    """The BF16 hi+lo log-likelihood with the adjoint from FP8 and from BF16 genotype
+    storage (FP8 codes widened to BF16 through registers, BF16 copied straight into LDS):
+    the same arithmetic in the same order, so log-likelihoods and gradients are identical
+    (ragged individual counts, one or more individual splits, padded particle rows)."""
+    torch = _torch()
+    s8, cfg, X, y, Xs = _sampler("n5000_p200_mala_bf16", "bf16x2", n=n, p=p, xfmt="fp8", move="mala")
+    s16, *_ = _sampler("n5000_p200_mala_bf16", "bf16x2", n=n, p=p, xfmt="bf16", move="mala")
+    b = torch.from_numpy(particles(M, X.shape[1], seed=p)).to("cuda", torch.float32)
+    g8, lp8 = s8.grad(b, 0.3)
+    g16, lp16 = s16.grad(b, 0.3)
+    assert torch.equal(g8, g16) and torch.equal(lp8, lp16)
+    bs = b.double().cpu().numpy()
+    ll_ref = likelihood.loglik(bs, Xs, y) + gt_prior.log_prior(bs, cfg.a, 0.3)
+    assert rel_err(lp16.cpu().numpy(), ll_ref).max() <= 1e-4
+
+
 @pytest.mark.parametrize("n,p,prec,M", [
     (130, 1, "fp64", 1), (130, 1, "bf16x2", 65), (70, 7, "fp32", 129), (200, 255, "fp64", 17),
     (200, 511, "bf16x2", 33), (200, 511, "fp32", 40), (64, 31, "bf16x2", 64), (66, 32, "bf16x2", 3),
