@@ -235,39 +235,56 @@ def gemm_flops(cfg) -> float:
     return f * (2.0 if cfg.move == "mala" else 1.0)
 
 
-def cpu_baseline(cfg, X, y, budget_s: float = 15.0):
-    """The oracle (FP64 NumPy, untuned) on a bounded sample: whole MALA/RW sweeps of a
-    subset of the particles, timed on the host's cores."""
-    from oracle import likelihood, smc
+def cpu_leg(workload: str, N: int = 1024, init_sweeps: int = 4, steps: int = 2) -> dict:
+    """The oracle (FP64 NumPy, untuned) running the sampler itself on the workload's data:
+    burn-in and the first scale steps of a whole SMC sweep at N particles, timed on this
+    process's threads.  Returns the algorithmic contraction throughput (the GPU line's
+    unit) and the full sweep's time extrapolated to the workload's particle count and
+    sweep count (the cost is linear in both)."""
+    from oracle import smc
+    from synth import CONFIGS, make_dataset
 
-    Xs, _, _ = likelihood.standardise(X)
-    prob = smc.Problem(Xs=Xs, y=y.astype(np.float64), a=cfg.a)
-    M = 1024
-    rng = np.random.default_rng(0)
-    beta = rng.normal(0, 0.05, size=(M, cfg.p))
-    if cfg.move == "mala":
-        ll, gl = prob.loglik_and_grad(beta)
-    else:
-        ll, gl = prob.loglik(beta), np.zeros_like(beta)
-    st = smc.State(beta=beta, ll=ll, gl=gl, logW=np.full(M, -math.log(M)))
-    sweep = smc.mala_sweep if cfg.move == "mala" else smc.rwm_sweep
-    sigma = np.full(cfg.p, 0.02)
+    cfg = CONFIGS[workload]
+    d = make_dataset(cfg)
+    run = cfg.replace(N=N, init_sweeps=init_sweeps)
     t0 = time.perf_counter()
-    sweeps = 0
-    while True:
-        sweep(prob, st, 1.0, 0.3, sigma, 0, sweeps, 1)
-        sweeps += 1
-        if time.perf_counter() - t0 >= budget_s or sweeps >= 200:
-            break
+    smc.run_config(run, d.X, d.y, T_stop=steps + 1)
     el = time.perf_counter() - t0
-    flops = gemm_flops(cfg) * M / cfg.N * sweeps
+    sweeps = init_sweeps + steps * cfg.sweeps
+    flops = gemm_flops(run) * sweeps
+    full_sweeps = cfg.init_sweeps + (cfg.T - 1) * cfg.sweeps
+    return {"value": flops / el / 1e12, "seconds": round(el, 2), "sweeps": sweeps, "N": N,
+            "full_sweep_s_extrapolated": round(el / sweeps * full_sweeps * cfg.N / N, 1)}
+
+
+def cpu_baseline(cfg) -> dict:
+    """The oracle timed on the host cores, all threads and one thread (BLAS and OpenMP
+    pinned to 1 in a child process), each on a bounded sample of whole sweeps (about 10 s)."""
+    import subprocess
     try:
         threads = len(os.sched_getaffinity(0))
     except AttributeError:
         threads = os.cpu_count()
-    return {"value": flops / el / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sweeps} {cfg.move.upper()} sweeps of {M} of the {cfg.N} particles "
-                      f"(n={cfg.n}, p={cfg.p}), FP64 NumPy, {el:.1f} s"}
+    allc = cpu_leg(cfg.name)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", cfg.name], env=env,
+                       capture_output=True, text=True, timeout=600)
+    one = json.loads(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 else {"error": r.stderr[-400:]}
+    sample = (f"oracle SMC on the {cfg.name} data (n={cfg.n}, p={cfg.p}, {cfg.move.upper()}): "
+              f"{allc['sweeps']} whole sweeps (burn-in + first scale steps) of {allc['N']} particles, "
+              f"FP64 NumPy, {allc['seconds']} s; throughput scaled per contraction flop")
+    out = {"value": round(allc["value"], 5), "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": sample,
+           "full_sweep_s_extrapolated": allc["full_sweep_s_extrapolated"],
+           "single_thread": {"value": round(one["value"], 6) if "value" in one else None, "unit": "TFLOP/s",
+                             "cores": 1, "seconds": one.get("seconds"),
+                             "full_sweep_s_extrapolated": one.get("full_sweep_s_extrapolated"),
+                             "error": one.get("error")}}
+    try:
+        out["cpu_model"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
+    return out
 
 
 def full_sweep(cfg, X, y, seed, **over):
@@ -286,37 +303,80 @@ def full_sweep(cfg, X, y, seed, **over):
     return mean, var, logz, el
 
 
-def ess_protocol(R: int = 8):
+def ess_protocol(R: int = 8, boot: int = 2000):
     """SPA sweep ESS/s on the n=5000, p=200 data: mixed-precision MALA (BF16 hi+lo, the
-    workload) vs plain FP32 random walk, each over R independent seeds, against an FP64
-    MALA reference path with 4N particles and 2S sweeps.  ESS_{t,j} = Var_t(beta_j) /
-    MSE(mean_{t,j}), summarised by the median over scales t >= 2 and coefficients j and
-    divided by the wall-clock of one full sweep (init + T-1 steps)."""
+    workload) vs plain FP32 random walk, R independent seeds each.
+
+    Reference: the pooled posterior-mean path of the stored FP64 oracle replicates
+    (tests/golden, 8 oracle sweeps of the same data and grid at N=4096, written by the
+    oracle alone); its own Monte Carlo variance var_ref (replicate variance / 8) is
+    subtracted from each method's MSE.  ESS_{t,j} = Var_t(beta_j) / (MSE_{t,j} - var_ref),
+    the posterior variance from the runs' variance paths, summarised by the median over
+    scales t >= 2 and coefficients j and divided by the wall-clock of one full sweep
+    (init + T-1 steps).  At equal posterior-mean error the ratio of the two methods' ESS/s
+    is the ratio of the times they need.  The interval is a bootstrap over the GPU seeds
+    of both methods (the reference fixed).  A GPU FP64 MALA run with 4N
+    particles and 2S sweeps is checked against the oracle pool (z per cell)."""
     from synth import CONFIGS, make_dataset
 
     mala, rwm = CONFIGS["n5000_p200_mala_bf16"], CONFIGS["n5000_p200_rwm_fp32"]
     d = make_dataset(mala)
-    ref_mean, ref_var, ref_logz, ref_s = full_sweep(mala, d.X, d.y, seed=9999, N=4 * mala.N,
-                                                    sweeps=2 * mala.sweeps, prec="fp64")
-    out = {"reference": {"move": "mala", "prec": "fp64", "N": 4 * mala.N,
-                         "sweeps": 2 * mala.sweeps, "seconds": round(ref_s, 2)}}
+    fx = np.load(os.path.join(ROOT, "tests", "golden", "replicates_n5000_p200_mala_bf16_N4096.npz"),
+                 allow_pickle=False)
+    orc = fx["mean"].astype(np.float64)                      # (R_o, T, p)
+    Ro, No = orc.shape[0], int(fx["N"])
+    ref = orc.mean(axis=0)
+    var_single = orc.var(axis=0, ddof=1)                     # one oracle run at N_o particles
+    var_ref = var_single / Ro
+    g_mean, g_var, _, g_s = full_sweep(mala, d.X, d.y, seed=9999, N=4 * mala.N, sweeps=2 * mala.sweeps,
+                                       prec="fp64")
+    # z of the GPU FP64 reference against the oracle pool (its variance scaled from N_o)
+    z = (g_mean - ref) / np.sqrt(var_ref + var_single * No / (4 * mala.N))
+    zc = z[1:].ravel()
+    out = {"reference": {"kind": "oracle replicate pool", "replicates": Ro, "N": No, "prec": "fp64",
+                         "check_gpu_fp64_mala_4N_2S": {"N": 4 * mala.N, "sweeps": 2 * mala.sweeps,
+                                                       "seconds": round(g_s, 2),
+                                                       "max_abs_z": round(float(np.max(np.abs(zc))), 3),
+                                                       "rms_z": round(float(np.sqrt(np.mean(zc * zc))), 3),
+                                                       "frac_abs_z_gt_3": round(float(np.mean(np.abs(zc) > 3)), 5),
+                                                       "cells": int(zc.size)}}}
+    runs = {}
     for tag, cfg in (("mala_bf16x2", mala), ("rwm_fp32", rwm)):
-        means, secs = [], []
+        means, vars_, secs = [], [], []
         for r in range(R):
-            m, _, _, el = full_sweep(cfg, d.X, d.y, seed=100 + r)
+            m, v, _, el = full_sweep(cfg, d.X, d.y, seed=100 + r)
             means.append(m)
+            vars_.append(v)
             secs.append(el)
-        means = np.stack(means)
-        mse = np.mean((means - ref_mean[None]) ** 2, axis=0)
-        ess = ref_var[1:] / np.maximum(mse[1:], 1e-300)
-        wall = float(np.median(secs))
-        ess_med = float(np.median(ess))
-        out[tag] = {"ess_median": round(ess_med, 2), "sweep_seconds": round(wall, 4),
-                    "ess_per_sec": round(ess_med / wall, 2),
-                    "rmse_mean_path": float(np.sqrt(np.mean(mse[1:]))),
+        runs[tag] = (np.stack(means), np.stack(vars_), float(np.median(secs)), cfg)
+    post_var = np.mean(np.concatenate([runs[k][1] for k in runs]), axis=0)   # Var_t(beta_j)
+
+    def summary(means, wall, orc_s):
+        rf = orc_s.mean(axis=0)
+        vr = orc_s.var(axis=0, ddof=1) / orc_s.shape[0]
+        mse_raw = np.mean((means - rf[None]) ** 2, axis=0)[1:]
+        mse = np.maximum(mse_raw - vr[1:], 1e-300)
+        ess = post_var[1:] / mse
+        return float(np.median(ess)), float(np.median(ess)) / wall, mse, mse_raw
+
+    for tag, (means, _, wall, cfg) in runs.items():
+        ess_med, ess_s, mse, mse_raw = summary(means, wall, orc)
+        out[tag] = {"ess_median": round(ess_med, 2), "sweep_seconds": round(wall, 4), "ess_per_sec": round(ess_s, 2),
+                    "rmse_mean_path": float(f"{np.sqrt(np.mean(mse)):.4e}"),
+                    "rmse_mean_path_uncorrected": float(f"{np.sqrt(np.mean(mse_raw)):.4e}"),
                     "sweeps_per_scale": cfg.sweeps, "N": cfg.N, "seeds": R}
-    out["mala_over_rwm_ess_per_sec"] = round(out["mala_bf16x2"]["ess_per_sec"] /
-                                             max(out["rwm_fp32"]["ess_per_sec"], 1e-300), 3)
+    ratio = out["mala_bf16x2"]["ess_per_sec"] / max(out["rwm_fp32"]["ess_per_sec"], 1e-300)
+    rng = np.random.default_rng(0)
+    bs = []
+    for _ in range(boot):
+        e = {}
+        for tag, (means, _, wall, _c) in runs.items():
+            e[tag] = summary(means[rng.integers(0, R, R)], wall, orc)[1]
+        bs.append(e["mala_bf16x2"] / max(e["rwm_fp32"], 1e-300))
+    out["mala_over_rwm_ess_per_sec"] = round(ratio, 3)
+    out["mala_over_rwm_ess_per_sec_ci95"] = [round(float(np.quantile(bs, 0.025)), 3),
+                                             round(float(np.quantile(bs, 0.975)), 3)]
+    out["bootstrap"] = boot
     return out
 
 
@@ -339,6 +399,8 @@ def main():
     ap.add_argument("--no-bandwidth", action="store_true", help="skip the weight / resampling / moment kernel leg")
     ap.add_argument("--bandwidth-only", action="store_true",
                     help="only run the weight / resampling / moment kernel leg and print its JSON")
+    ap.add_argument("--cpu-leg", default=None, metavar="WORKLOAD",
+                    help="only time the oracle leg of the CPU baseline on this process's threads (JSON)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device copy three times (the reference "
                          "launch for scaling FETCH_SIZE / WRITE_SIZE counters)")
@@ -349,6 +411,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.cpu_leg:
+        print(json.dumps(cpu_leg(args.cpu_leg)))
         return
 
     import torch
@@ -443,7 +508,7 @@ def main():
     if not args.no_ess:
         out["ess"] = ess_protocol(args.ess_seeds)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, d.X, d.y)
+        out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))
 
 

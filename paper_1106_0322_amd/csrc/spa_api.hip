@@ -969,7 +969,9 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
     set_err(h, SPA_ERR_ALLOC, "hipHostMalloc failed");
     return fail(SPA_ERR_ALLOC);
   }
-  if ((st = ensure_op(h, h->op, h->prec, h->PP, h->Npad)) != SPA_OK) return fail(st);
+  // the FP8 multi-term sampler packs its proposals into FP8 terms and contracts the FP8
+  // genotype copy: the BF16 operand and genotype copies are made only if a BF16 call asks
+  if (!h->f8_terms && (st = ensure_op(h, h->op, h->prec, h->PP, h->Npad)) != SPA_OK) return fail(st);
 
   // ---- operand preparation (once)
   he = hipMemcpyAsync(h->dX, X_host, (size_t)n * p, hipMemcpyHostToDevice, h->stream);
@@ -979,7 +981,7 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
     return fail(SPA_ERR_HIP);
   }
   launch_col_stats(h->dX, h->dy, n, p, h->mu, h->s, h->inv_s, h->ytil, h->dbad, h->stream);
-  if ((st = ensure_xpack(h, h->prec)) != SPA_OK) return fail(st);
+  if (!h->f8_terms && (st = ensure_xpack(h, h->prec)) != SPA_OK) return fail(st);
   if (h->move == SPA_MOVE_SINGLE) {
     if ((st = dalloc(h, &h->xs_ss, h->psz * (size_t)p * h->n_pad)) != SPA_OK) return fail(st);
     if ((st = dalloc(h, &h->yv_ss, h->psz * (size_t)h->n_pad)) != SPA_OK) return fail(st);
