@@ -207,8 +207,9 @@ def bandwidth_leg(cfg, X, y, reps: int = 10):
         states.append(torch.from_numpy(lw))
     g.set_timing(True, classes=["reweight", "lse_resample", "moments"])
     resampled = 0
+    t0 = min(40, cfg.T - 1)
     for r in range(2 * reps):
-        g.set_state(beta, states[r % 2], 40, 0.1)
+        g.set_state(beta, states[r % 2], t0, 0.1)
         resampled += int(g.step()["resampled"])
     t = g.timing()
     g.close()

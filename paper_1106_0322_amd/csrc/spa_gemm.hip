@@ -21,7 +21,9 @@
 // registers (a lane of an eta^T block holds four individuals of one particle, i.e. the K
 // slots of an MFMA B fragment).  Softplus sums: per lane and tile, sum max(eta, 0) plus
 // one log of prod (1 + exp(-|eta|)) (the product of at most 16 factors in (1, 2] cannot
-// overflow), accumulated across tiles in FP64 in a fixed order.  With S > 1 each split
+// overflow), accumulated across tiles in FP64 in a fixed order; in reduced precision
+// sum max(eta, 0) is taken as half of sum |eta| (the standardised genotypes are centred,
+// so sum_k eta_ik = 0 over the real individuals).  With S > 1 each split
 // writes partial sums that a finalize kernel adds in split order.
 #include "spa_common.hpp"
 #include "spa_internal.hpp"
@@ -408,21 +410,23 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
       }                                                                                           \
       spl[pb] += sp;                                                                              \
     } else {                                                                                      \
-      /* reduced precision: the operand carries log2(e), so z = eta log2(e) */                   \
+      /* reduced precision: the operand carries log2(e), so z = eta log2(e); the genotypes  */    \
+      /* are centred, so sum_k eta_ik = 0 over the real individuals and sum_k max(z, 0) is  */    \
+      /* half of sum_k |z| (one add with an abs modifier per element instead of two ops)   */     \
       float prod = 1.0f, mx = 0.0f;                                                               \
       _Pragma("unroll") for (int b = 0; b < QB; ++b) _Pragma("unroll") for (int v = 0; v < 4; ++v) { \
         const float z = acc[b][pb][v] - moff[pb];                                                 \
         const float e = fast_exp2(-fabsf(z));                                                     \
         if (!(MASKED) || (tile0 + (q * QB + b) * 16 + T::crow(lg, v)) < n) {                      \
           prod = fmaf(prod, e, prod);                                                             \
-          mx += fmaxf(z, 0.0f);                                                                   \
+          mx += fabsf(z);                                                                         \
         }                                                                                         \
         if constexpr (GRAD) {                                                                     \
           const float rc = fast_rcp(1.0f + e);                                                    \
           sig[b][pb][v] = z >= 0.0f ? rc : e * rc;                                                \
         }                                                                                         \
       }                                                                                           \
-      spl[pb] += static_cast<double>(0.6931471805599453f * (mx + fast_log2(prod)));              \
+      spl[pb] += static_cast<double>(0.6931471805599453f * (0.5f * mx + fast_log2(prod)));       \
     }                                                                                             \
   }
       SPA_ELEMENTWISE(MASKED)
