@@ -144,7 +144,8 @@ struct spa_smc {
   double t_ms[SPA_TIMING_CLASSES] = {0};
   long long t_cnt[SPA_TIMING_CLASSES] = {0};
   // EM MAP estimates (FP64 standardised columns and labels) and the MAP path
-  double *map_xs = nullptr, *map_yv = nullptr;
+  uint8_t *map_codes = nullptr;                       // p x n_pad genotype codes (EM)
+  double *map_xv = nullptr, *map_yv = nullptr;        // p x 4 code values, n_pad labels
   bool map_on = false;
   int map_outer = 0, map_inner = 0, map_last_row = -1;
   double *map_path = nullptr, *map_lp = nullptr;        // T x p, T
@@ -637,11 +638,13 @@ spa_status single_site_cycles(spa_smc *h, int t, int cycles, double lam) {
 }
 
 spa_status ensure_map_cols(spa_smc *h) {
-  if (h->map_xs) return SPA_OK;
+  if (h->map_codes) return SPA_OK;
   spa_status st;
-  if ((st = dalloc(h, &h->map_xs, 8 * (size_t)h->p * h->n_pad)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_codes, (size_t)h->p * h->n_pad)) != SPA_OK) return st;
+  if ((st = dalloc(h, &h->map_xv, 8 * 4 * (size_t)h->p)) != SPA_OK) return st;
   if ((st = dalloc(h, &h->map_yv, 8 * (size_t)h->n_pad)) != SPA_OK) return st;
-  SPA_CK(h, launch_map_cols(h->dX, h->dy, h->n, h->p, h->n_pad, h->mu, h->s, h->map_xs, h->map_yv, h->stream));
+  SPA_CK(h, launch_map_cols(h->dX, h->dy, h->n, h->p, h->n_pad, h->mu, h->s, h->map_codes, h->map_xv, h->map_yv,
+                            h->stream));
   return SPA_OK;
 }
 
@@ -650,7 +653,8 @@ spa_status run_map_em(spa_smc *h, const void *beta0, bool in_f64, int M, double 
   spa_status st;
   if ((st = ensure_map_cols(h)) != SPA_OK) return st;
   MapArgs a{};
-  a.xs = h->map_xs;
+  a.codes = h->map_codes;
+  a.xv = h->map_xv;
   a.yv = h->map_yv;
   a.beta0 = beta0;
   a.mode = mode;

@@ -5,13 +5,18 @@
 // weighted-L1 logistic problem by cyclic coordinate ascent with the curvature bound n/4,
 // beta_j <- S(beta_j + 4 g_j / n, 4 w_j / n), g_j = sum_k (y_k - sigma(eta_k)) X_std,kj.
 //
-// One workgroup (16 wave64s) per start point.  Thread t keeps the linear predictor eta and
-// sigma(eta) of individuals t, t+1024, ... in registers; the coefficients and weights live
-// in LDS.  Each coordinate update is one block-wide reduction of g_j (wave sums, then the
-// 16 wave partials added in a fixed order by every thread, so all threads take the same
-// value) followed by a register update of eta and sigma when the coordinate moved.  The
-// updates of one start point are sequential, so its latency is set by the per-thread
-// column loads and the reduction: the widest workgroup keeps both short.
+// One workgroup (16 wave64s) per start point.  Thread t keeps E_k = exp(-eta_k) and
+// sigma(eta_k) = 1/(1 + E_k) of individuals t, t+1024, ... in registers; the coefficients,
+// the weights and the standardised values of the genotype codes live in LDS.  A column of
+// standardised genotypes takes only three values x_c = (c - mu_j)/s_j, c = 0, 1, 2, so a
+// move beta_j += delta multiplies every E_k by one of the three constants exp(-delta x_c):
+// one exponential per lane (lane l computes the one of code l mod 4; code 3 marks padded
+// individuals, x = 0) broadcast by a lane shuffle, then per individual one multiply and a
+// reciprocal (hardware estimate refined by two Newton steps).  The columns are read as
+// one-byte codes.  As in the oracle, eta is recomputed from the coefficients at the start
+// of every coordinate sweep, which also bounds the rounding of the products to one sweep.
+// Each coordinate update is one block-wide reduction of g_j (wave sums, then the 16 wave
+// partials added in a fixed order by every thread, so all threads take the same value).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,41 +30,67 @@ namespace {
 constexpr int kMapThreads = 1024;
 constexpr int kMapWaves = kMapThreads / 64;
 
-__device__ __forceinline__ double sigmoid(double e) { return 1.0 / (1.0 + exp(-e)); }
+// 1 / (1 + e) for e >= 0 (e = +inf gives 0): hardware reciprocal and two Newton steps.
+__device__ __forceinline__ double inv1p(double e) {
+  const double d = 1.0 + e;
+  if (!(d < INFINITY)) return 0.0;
+  double r = __builtin_amdgcn_rcp(d);
+  double q = fma(-d, r, 1.0);
+  r = fma(r, q, r);
+  q = fma(-d, r, 1.0);
+  return fma(r, q, r);
+}
 
 template <typename IT, int R>
 __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
-  __shared__ double bl[kMapMaxP], wl[kMapMaxP];
+  __shared__ double bl[kMapMaxP], wl[kMapMaxP], xv[kMapMaxP][4];
   __shared__ double part[2][kMapWaves];
   __shared__ double red[kMapWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = blockIdx.x;                      // start point
   const int n = a.n, n_pad = a.n_pad, p = a.p;
-  const double *xs = a.xs;                       // p x n_pad, zero padded
+  const uint8_t *codes = a.codes;                // p x n_pad, 3 in padded individuals
   const IT *b0 = reinterpret_cast<const IT *>(a.beta0) + (size_t)s * p;
   const Prior pr = a.prior;
   const double inv_n4 = 4.0 / static_cast<double>(n);
 
-  for (int j = tid; j < p; j += kMapThreads) bl[j] = static_cast<double>(b0[j]);
+  for (int j = tid; j < p; j += kMapThreads) {
+    bl[j] = static_cast<double>(b0[j]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xv[j][c] = a.xv[4 * j + c];
+  }
   __syncthreads();
-  double eta[R], sg[R], yk[R];
+  double E[R], sg[R], yk[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = tid + kMapThreads * r;
-    eta[r] = 0.0;
     yk[r] = k < n_pad ? a.yv[k] : 0.0;
   }
-  for (int j = 0; j < p; ++j) {
-    const double bj = bl[j];
-    const double *col = xs + (size_t)j * n_pad;
+  auto load_codes = [&](const int j, int (&c)[R]) {
+    const uint8_t *col = codes + (size_t)j * n_pad;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int k = tid + kMapThreads * r;
-      if (k < n_pad) eta[r] += bj * col[k];
+      c[r] = k < n_pad ? static_cast<int>(col[k]) : 3;
     }
-  }
+  };
+  // eta from the coefficients (the sweep's fresh linear predictor), then E and sigma
+  auto refresh = [&](double (&eta)[R]) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) sg[r] = sigmoid(eta[r]);
+    for (int r = 0; r < R; ++r) eta[r] = 0.0;
+    for (int j = 0; j < p; ++j) {
+      int c[R];
+      load_codes(j, c);
+      const double bj = bl[j];
+#pragma unroll
+      for (int r = 0; r < R; ++r) eta[r] += bj * xv[j][c[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      E[r] = exp(-eta[r]);
+      sg[r] = inv1p(E[r]);
+    }
+  };
 
   int parity = 0;
   for (int it = 0; it < a.outer; ++it) {
@@ -67,34 +98,24 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
     for (int j = tid; j < p; j += kMapThreads)
       wl[j] = pr.inf ? 1.0 / pr.lam : (pr.a + 1.0) / (pr.a * pr.lam + fabs(bl[j]));
     __syncthreads();
-    // up to 6 individuals per thread, column j+1 is loaded while coordinate j is reduced
-    // and updated (more would not fit the registers of a 1024-thread workgroup)
-    constexpr bool PF = R <= 6;
-    auto load_col = [&](const int j, double (&v)[R]) {
-      const double *c = xs + (size_t)j * n_pad;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int k = tid + kMapThreads * r;
-        v[r] = k < n_pad ? c[k] : 0.0;
-      }
-    };
     for (int sw = 0; sw < a.inner; ++sw) {
-      double xn[R];
-      if constexpr (PF) load_col(0, xn);
+      __syncthreads();                           // the previous sweep's last coefficient
+      {
+        double eta[R];
+        refresh(eta);
+      }
+      int cn[R];
+      load_codes(0, cn);
       for (int j = 0; j < p; ++j) {
         // read beta_j before the barrier: thread 0 overwrites it after the barrier
         const double bj = bl[j], wj = wl[j];
-        double x[R];
-        if constexpr (PF) {
+        int c[R];
 #pragma unroll
-          for (int r = 0; r < R; ++r) x[r] = xn[r];
-          if (j + 1 < p) load_col(j + 1, xn);
-        } else {
-          load_col(j, x);
-        }
+        for (int r = 0; r < R; ++r) c[r] = cn[r];
+        if (j + 1 < p) load_codes(j + 1, cn);   // next column's codes in flight
         double g = 0.0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) g += (yk[r] - sg[r]) * x[r];   // padded individuals: x = 0
+        for (int r = 0; r < R; ++r) g += (yk[r] - sg[r]) * xv[j][c[r]];   // padded: x = 0
         g = wave_sum(g);
         if (lane == 0) part[parity][wave] = g;
         __syncthreads();
@@ -106,10 +127,11 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
         const double nb = z > thr ? z - thr : (z < -thr ? z + thr : 0.0);
         const double delta = nb - bj;
         if (delta != 0.0) {                      // uniform: every thread holds the same values
+          const double cl = exp(-delta * xv[j][lane & 3]);   // lanes 0..3 hold codes 0..3
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            eta[r] += delta * x[r];
-            sg[r] = sigmoid(eta[r]);
+            E[r] *= __shfl(cl, c[r], 64);
+            sg[r] = inv1p(E[r]);
           }
         }
         if (tid == 0) bl[j] = nb;
@@ -118,6 +140,8 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
   }
   __syncthreads();
   // log posterior at the mode: sum_k [y eta - softplus(eta)] + sum_j log Gt(beta_j)
+  double eta[R];
+  refresh(eta);
   double acc = 0.0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -136,17 +160,19 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
   for (int j = tid; j < p; j += kMapThreads) a.mode[(size_t)s * p + j] = bl[j];
 }
 
-// Standardised genotype columns in FP64 for the EM kernel.
+// Genotype codes per column (3 in padded individuals), the standardised value of each code
+// (x_c = (c - mu_j)/s_j, 0 for code 3) and the labels in FP64, for the EM kernel.
 __global__ void map_cols_kernel(const uint8_t *__restrict__ X, int n, int p, int n_pad,
                                 const double *__restrict__ mu, const double *__restrict__ sd,
-                                double *__restrict__ xs, double *__restrict__ yv,
+                                uint8_t *__restrict__ codes, double *__restrict__ xv, double *__restrict__ yv,
                                 const uint8_t *__restrict__ y) {
   const size_t total = (size_t)p * n_pad;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int j = static_cast<int>(idx / n_pad), k = static_cast<int>(idx % n_pad);
-    xs[idx] = k < n ? (static_cast<double>(X[(size_t)k * p + j]) - mu[j]) / sd[j] : 0.0;
+    codes[idx] = k < n ? X[(size_t)k * p + j] : uint8_t(3);
     if (j == 0) yv[k] = k < n ? static_cast<double>(y[k]) : 0.0;
+    if (k < 4) xv[4 * j + k] = k < 3 ? (static_cast<double>(k) - mu[j]) / sd[j] : 0.0;
   }
 }
 
@@ -216,8 +242,11 @@ hipError_t launch_em_t(const MapArgs &a, hipStream_t st) {
   const int R = (a.n_pad + kMapThreads - 1) / kMapThreads;
   if (R <= 1) launch_em_r<IT, 1>(a, st);
   else if (R <= 2) launch_em_r<IT, 2>(a, st);
+  else if (R <= 3) launch_em_r<IT, 3>(a, st);
   else if (R <= 4) launch_em_r<IT, 4>(a, st);
+  else if (R <= 5) launch_em_r<IT, 5>(a, st);
   else if (R <= 6) launch_em_r<IT, 6>(a, st);
+  else if (R <= 8) launch_em_r<IT, 8>(a, st);
   else if (R <= 10) launch_em_r<IT, 10>(a, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
@@ -228,10 +257,10 @@ hipError_t launch_em_t(const MapArgs &a, hipStream_t st) {
 int map_max_n() { return kMapThreads * 10; }
 
 hipError_t launch_map_cols(const uint8_t *X, const uint8_t *y, int n, int p, int n_pad, const double *mu,
-                           const double *sd, double *xs, double *yv, hipStream_t st) {
+                           const double *sd, uint8_t *codes, double *xv, double *yv, hipStream_t st) {
   const size_t total = (size_t)p * n_pad;
   const int grid = static_cast<int>((total + 255) / 256 < 4096 ? (total + 255) / 256 : 4096);
-  hipLaunchKernelGGL(map_cols_kernel, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, mu, sd, xs, yv, y);
+  hipLaunchKernelGGL(map_cols_kernel, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, mu, sd, codes, xv, yv, y);
   return hipGetLastError();
 }
 

@@ -11,7 +11,8 @@ namespace spa {
 constexpr int kMapMaxP = 512;
 
 struct MapArgs {
-  const double *xs;     // p x n_pad standardised genotypes (FP64), zero padded
+  const uint8_t *codes; // p x n_pad genotype codes 0/1/2, 3 in padded individuals
+  const double *xv;     // p x 4 standardised value of each code ((c - mu_j)/s_j; 0 for code 3)
   const double *yv;     // n_pad labels (FP64), zero padded
   const void *beta0;    // M x p start points (FP32 or FP64)
   double *mode;         // M x p modes (output)
@@ -24,7 +25,7 @@ struct MapArgs {
 // Largest n the EM kernel keeps in registers.
 int map_max_n();
 hipError_t launch_map_cols(const uint8_t *X, const uint8_t *y, int n, int p, int n_pad, const double *mu,
-                           const double *sd, double *xs, double *yv, hipStream_t st);
+                           const double *sd, uint8_t *codes, double *xv, double *yv, hipStream_t st);
 hipError_t launch_map_em(bool in_f64, const MapArgs &a, hipStream_t st);
 hipError_t launch_best_particle(bool f64, const void *beta, const double *ll, int M, int p, const Prior &pr,
                                 int *best, hipStream_t st);
