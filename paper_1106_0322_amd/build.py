@@ -41,6 +41,36 @@ def _compile(src: str) -> str:
     return obj
 
 
+# Host-only AddressSanitizer copy of the library for the CPU tests of the C-ABI validation
+# paths (device code is compiled as usual; the sanitizer runtime is preloaded by the test).
+ASAN_LIB = os.path.join(BUILD, "libspa_smc_asan.so")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-shared-libasan"]
+
+
+def build_asan(verbose: bool = False) -> str:
+    os.makedirs(os.path.join(BUILD, "asan"), exist_ok=True)
+
+    def one(src: str) -> str:
+        obj = os.path.join(BUILD, "asan", os.path.splitext(src)[0] + ".o")
+        cmd = [_hipcc(), *HIPCC_FLAGS, *ASAN_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (host sanitizer) failed for {src}:\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    tmp = ASAN_LIB + ".tmp"
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *ASAN_FLAGS, "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (host sanitizer) failed:\n{r.stderr}")
+    os.replace(tmp, ASAN_LIB)
+    if verbose:
+        print(f"built {ASAN_LIB}")
+    return ASAN_LIB
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
