@@ -308,39 +308,47 @@ def ess_protocol(R: int = 8, boot: int = 2000):
     """SPA sweep ESS/s on the n=5000, p=200 data: mixed-precision MALA (BF16 hi+lo, the
     workload) vs plain FP32 random walk, R independent seeds each.
 
-    Reference: the pooled posterior-mean path of the stored FP64 oracle replicates
-    (tests/golden, 8 oracle sweeps of the same data and grid at N=4096, written by the
-    oracle alone); its own Monte Carlo variance var_ref (replicate variance / 8) is
-    subtracted from each method's MSE.  ESS_{t,j} = Var_t(beta_j) / (MSE_{t,j} - var_ref),
+    Reference: the pooled posterior-mean path of stored FP64 oracle replicates (tests/golden,
+    8 oracle sweeps of the same data and grid with 2S = 20 MALA sweeps per scale at N=2048,
+    written by the oracle alone): at finite N the path depends on the sweeps per scale, so
+    a reference with twice the sweeps of the compared runs does not share their mixing
+    error; its own Monte Carlo variance var_ref (replicate variance / 8) is subtracted from
+    each method's MSE.  ESS_{t,j} = Var_t(beta_j) / (MSE_{t,j} - var_ref),
     the posterior variance from the runs' variance paths, summarised by the median over
     scales t >= 2 and coefficients j and divided by the wall-clock of one full sweep
     (init + T-1 steps).  At equal posterior-mean error the ratio of the two methods' ESS/s
     is the ratio of the times they need.  The interval is a bootstrap over the GPU seeds
     of both methods (the reference fixed).  A GPU FP64 MALA run with 4N
-    particles and 2S sweeps is checked against the oracle pool (z per cell)."""
+    particles and 2S sweeps is checked against that pool and against the S = 10 oracle pool
+    (N=4096) of the sweep-parity test (z per cell)."""
     from synth import CONFIGS, make_dataset
 
     mala, rwm = CONFIGS["n5000_p200_mala_bf16"], CONFIGS["n5000_p200_rwm_fp32"]
     d = make_dataset(mala)
-    fx = np.load(os.path.join(ROOT, "tests", "golden", "replicates_n5000_p200_mala_bf16_N4096.npz"),
-                 allow_pickle=False)
+    golden = os.path.join(ROOT, "tests", "golden")
+    fx = np.load(os.path.join(golden, "replicates_n5000_p200_mala_S20_N2048.npz"), allow_pickle=False)
+    fx10 = np.load(os.path.join(golden, "replicates_n5000_p200_mala_bf16_N4096.npz"), allow_pickle=False)
     orc = fx["mean"].astype(np.float64)                      # (R_o, T, p)
     Ro, No = orc.shape[0], int(fx["N"])
-    ref = orc.mean(axis=0)
-    var_single = orc.var(axis=0, ddof=1)                     # one oracle run at N_o particles
-    var_ref = var_single / Ro
     g_mean, g_var, _, g_s = full_sweep(mala, d.X, d.y, seed=9999, N=4 * mala.N, sweeps=2 * mala.sweeps,
                                        prec="fp64")
-    # z of the GPU FP64 reference against the oracle pool (its variance scaled from N_o)
-    z = (g_mean - ref) / np.sqrt(var_ref + var_single * No / (4 * mala.N))
-    zc = z[1:].ravel()
-    out = {"reference": {"kind": "oracle replicate pool", "replicates": Ro, "N": No, "prec": "fp64",
+
+    def zcheck(pool, n_pool):
+        """z per cell of the GPU FP64 4N/2S path against an oracle pool (variance of one
+        4N run scaled from the pool's particle count)."""
+        vs = pool.var(axis=0, ddof=1)
+        z = (g_mean - pool.mean(axis=0)) / np.sqrt(vs / pool.shape[0] + vs * n_pool / (4 * mala.N))
+        zc = z[1:].ravel()
+        return {"max_abs_z": round(float(np.max(np.abs(zc))), 3), "rms_z": round(float(np.sqrt(np.mean(zc * zc))), 3),
+                "frac_abs_z_gt_3": round(float(np.mean(np.abs(zc) > 3)), 5), "cells": int(zc.size)}
+
+    out = {"reference": {"kind": "oracle replicate pool", "replicates": Ro, "N": No, "sweeps": int(fx["sweeps"]),
+                         "prec": "fp64",
                          "check_gpu_fp64_mala_4N_2S": {"N": 4 * mala.N, "sweeps": 2 * mala.sweeps,
                                                        "seconds": round(g_s, 2),
-                                                       "max_abs_z": round(float(np.max(np.abs(zc))), 3),
-                                                       "rms_z": round(float(np.sqrt(np.mean(zc * zc))), 3),
-                                                       "frac_abs_z_gt_3": round(float(np.mean(np.abs(zc) > 3)), 5),
-                                                       "cells": int(zc.size)}}}
+                                                       "vs_reference_pool_S20": zcheck(orc, No),
+                                                       "vs_oracle_pool_S10_N4096": zcheck(
+                                                           fx10["mean"].astype(np.float64), int(fx10["N"]))}}}
     runs = {}
     for tag, cfg in (("mala_bf16x2", mala), ("rwm_fp32", rwm)):
         means, vars_, secs = [], [], []
