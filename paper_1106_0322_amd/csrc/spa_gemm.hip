@@ -558,6 +558,238 @@ __attribute__((amdgpu_waves_per_eu((Shape<P, PP>::NW / 4), (Shape<P, PP>::NW / 4
   }
 }
 
+// Split-marker form of the BF16 hi+lo contraction with the adjoint, for rows of 384 or 512
+// markers.  There one wave's coefficient fragments (hi and lo, 8 k-steps of 32 markers per
+// 256) and adjoint accumulators (16 blocks of 16 markers per 256) would take all of a
+// SIMD's registers; here the two waves w and w+4 of a SIMD share a block of 16 particles
+// and each holds one half of the markers: it computes the forward partial sums of its half,
+// the two halves are added through LDS (float addition commutes, so both waves hold the
+// same eta), both evaluate the same elementwise step, and each accumulates the adjoint of
+// its half.  Two waves per SIMD (8 per workgroup, 64 particles).  Tiles of 32 individuals
+// are staged through registers (the next tile's 16-byte chunks are loaded during a tile and
+// written, FP8 codes widened to BF16, into the single LDS stage between two barriers),
+// which leaves room in LDS for the exchange.  The same arithmetic per element as
+// loglik_kernel; a forward sum is formed as the sum of two half sums.  (Splitting the
+// elementwise step between the two waves, with a second exchange of the logistic values,
+// was measured slower: one more barrier per tile costs more than half the vector work.)
+template <int PP, bool FP8>
+__global__ __attribute__((amdgpu_flat_work_group_size(64, 512))) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void loglik_wide_kernel(GemmArgs args) {
+  constexpr Prec P = Prec::BF16X2;
+  using T = GT<P>;
+  using FR = bf16x8;
+  using AC = f32x4;
+  using LX = __bf16;
+  using XG = typename std::conditional<FP8, uint8_t, LX>::type;
+  constexpr int KS = 32, KV = 8, NT = 32, NTHR = 512, WGP = 64;
+  constexpr int H = PP / 2;                      // markers per half
+  constexpr int NKH = H / KS, NMH = H / 16;      // forward k-steps, adjoint blocks per half
+  constexpr int CPR = PP * 2 / 16, CX = CPR + 1;  // individual-major rows (BF16 chunks)
+  constexpr int CPT = NT * 2 / 16, CT = CPT + 1;  // marker-major rows
+  constexpr int XS = NT * CX, TS = PP * CT;       // slots of the two regions
+  // staged 16-byte chunks of the source (FP8: 16 codes; BF16: 8 values)
+  constexpr int EPC = 16 / (int)sizeof(XG);      // elements per staged chunk
+  constexpr int NCX = NT * PP / EPC, NCT = PP * NT / EPC;
+  constexpr int RX = (NCX + NTHR - 1) / NTHR, RT = (NCT + NTHR - 1) / NTHR;
+  static_assert(PP == 384 || PP == 512, "rows of 384 or 512 markers");
+
+  extern __shared__ __align__(16) uint4 smem[];   // XS + TS slots, then the exchange
+  float *xbuf = reinterpret_cast<float *>(smem + XS + TS);   // 8 waves x 64 lanes x 8 floats
+
+  const int S = args.S;
+  const int g8 = 8 / S;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int split = xcd / g8;
+  const int ptile = slot * g8 + (xcd % g8);
+  const int ntiles_p = (args.M + WGP - 1) / WGP;
+  if (ptile >= ntiles_p) return;
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lr = lane & 15, lg = lane >> 4;
+  const int half = wave >> 2, pblk = wave & 3;
+  const int wbase = ptile * WGP + pblk * 16;
+  const int n = args.n, n_pad = args.n_pad;
+  const int chunk = ((n_pad + S - 1) / S + NT - 1) / NT * NT;
+  const int i0 = min(n_pad, split * chunk);
+  const int i1 = min(min(n_pad, i0 + chunk), (n + NT - 1) / NT * NT);
+  const int ntiles = max(0, (i1 - i0) / NT);
+  const int tmask = (ntiles > 0 && i0 + ntiles * NT > n) ? ntiles - 1 : ntiles;   // tile with padding
+
+  FR bh[NKH], bl[NKH];
+  float moff;
+  {
+    const size_t row = static_cast<size_t>(wbase + lr);
+    const __bf16 *sh = reinterpret_cast<const __bf16 *>(args.Bhi) + row * PP + half * H + lg * KV;
+    const __bf16 *sl = reinterpret_cast<const __bf16 *>(args.Blo) + row * PP + half * H + lg * KV;
+#pragma unroll
+    for (int ks = 0; ks < NKH; ++ks) {
+      bh[ks] = *reinterpret_cast<const FR *>(sh + ks * KS);
+      bl[ks] = *reinterpret_cast<const FR *>(sl + ks * KS);
+    }
+    moff = static_cast<float>(args.moff[row]);
+  }
+  AC G[NMH];
+#pragma unroll
+  for (int mb = 0; mb < NMH; ++mb) G[mb] = AC{0, 0, 0, 0};
+  double spl = 0.0;
+
+  const uint8_t *gxk = reinterpret_cast<const uint8_t *>(args.Xk);
+  const uint8_t *gxt = reinterpret_cast<const uint8_t *>(args.Xt);
+  uint4 sx[RX], st[RT];
+  auto load_tile = [&](const int tile0) {   // the tile's chunks into registers
+#pragma unroll
+    for (int u = 0; u < RX; ++u) {
+      const int c = tid + u * NTHR;
+      if (c < NCX) {
+        const int r = c / (PP / EPC), cc = c % (PP / EPC);
+        sx[u] = *reinterpret_cast<const uint4 *>(gxk + ((size_t)(tile0 + r) * PP + cc * EPC) * sizeof(XG));
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RT; ++u) {
+      const int c = tid + u * NTHR;
+      if (c < NCT) {
+        const int r = c / (NT / EPC), cc = c % (NT / EPC);
+        st[u] = *reinterpret_cast<const uint4 *>(gxt + ((size_t)r * n_pad + tile0 + cc * EPC) * sizeof(XG));
+      }
+    }
+  };
+  auto store_tile = [&]() {   // registers -> the LDS stage (FP8 widened to BF16)
+#pragma unroll
+    for (int u = 0; u < RX; ++u) {
+      const int c = tid + u * NTHR;
+      if (c < NCX) {
+        const int r = c / (PP / EPC), cc = c % (PP / EPC);
+        if constexpr (FP8) store_fp8_as_bf16(reinterpret_cast<__bf16 *>(smem + r * CX + 2 * cc), sx[u]);
+        else smem[r * CX + cc] = sx[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RT; ++u) {
+      const int c = tid + u * NTHR;
+      if (c < NCT) {
+        const int r = c / (NT / EPC), cc = c % (NT / EPC);
+        if constexpr (FP8) store_fp8_as_bf16(reinterpret_cast<__bf16 *>(smem + XS + r * CT + 2 * cc), st[u]);
+        else smem[XS + r * CT + cc] = st[u];
+      }
+    }
+  };
+
+  if (ntiles > 0) load_tile(i0);
+  for (int it = 0; it < ntiles; ++it) {
+    const int tile0 = i0 + it * NT;
+    __syncthreads();                             // every wave is done with the previous tile
+    store_tile();
+    __syncthreads();                             // this tile is in LDS
+    if (it + 1 < ntiles) load_tile(tile0 + NT);  // the next tile in flight during this one
+    const uint4 *sX = smem, *sXt = smem + XS;
+    // forward partial sums of this half: eta^T blocks of the tile's two 16-individual blocks
+    AC acc[2] = {AC{0, 0, 0, 0}, AC{0, 0, 0, 0}};
+#pragma unroll
+    for (int ks = 0; ks < NKH; ++ks) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const FR a = reinterpret_cast<const FR *>(sX + (b * 16 + lr) * CX)[(half * NKH + ks) * KS / KV + lg];
+        acc[b] = T::mfma(a, bh[ks], acc[b]);
+        acc[b] = T::mfma(a, bl[ks], acc[b]);
+      }
+    }
+    {
+      constexpr int D = kPrefetch;
+      __builtin_amdgcn_sched_group_barrier(0x100, 2 * D, 0);
+#pragma unroll
+      for (int ks = 0; ks < NKH; ++ks) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+        if (ks + D < NKH) __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+      }
+    }
+    // exchange the half sums with the other wave of the particle block
+    float *mine = xbuf + ((size_t)wave * 64 + lane) * 8;
+    const float *other = xbuf + ((size_t)(wave ^ 4) * 64 + lane) * 8;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) *reinterpret_cast<AC *>(mine + 4 * b) = acc[b];
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[b] += *reinterpret_cast<const AC *>(other + 4 * b);
+    // elementwise (the same in both waves of the pair)
+    float prod = 1.0f, mx = 0.0f, sig[2][4];
+    const bool masked = it == tmask;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float z = acc[b][v] - moff;
+        const float e = fast_exp2(-fabsf(z));
+        if (!masked || (tile0 + b * 16 + T::crow(lg, v)) < n) {
+          prod = fmaf(prod, e, prod);
+          mx += fabsf(z);
+        }
+        const float rc = fast_rcp(1.0f + e);
+        sig[b][v] = z >= 0.0f ? rc : e * rc;
+      }
+    spl += static_cast<double>(0.6931471805599453f * (0.5f * mx + fast_log2(prod)));
+    bf16x8 rh, rl;
+#pragma unroll
+    for (int j = 0; j < 8; j += 2) {
+      const f32x2 v = {sig[j >> 2][j & 3], sig[j >> 2][(j & 3) + 1]};
+      const bf16x2 h = __builtin_convertvector(v, bf16x2);
+      const f32x2 r = v - __builtin_convertvector(h, f32x2);
+      const bf16x2 l = __builtin_convertvector(r, bf16x2);
+      rh[j] = h[0];
+      rh[j + 1] = h[1];
+      rl[j] = l[0];
+      rl[j + 1] = l[1];
+    }
+    // adjoint of this half: G^T (markers x particles) += X_tile^T . sigma^T
+#pragma unroll
+    for (int mb = 0; mb < NMH; ++mb) {
+      const bf16x8 a = *reinterpret_cast<const bf16x8 *>(sXt + ((half * NMH + mb) * 16 + lr) * CT + lg);
+      G[mb] = T::mfma(a, rh, G[mb]);
+      G[mb] = T::mfma(a, rl, G[mb]);
+    }
+    {
+      constexpr int D = kPrefetch;
+      __builtin_amdgcn_sched_group_barrier(0x100, D, 1);
+#pragma unroll
+      for (int mb = 0; mb < NMH; ++mb) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 2, 1);
+        if (mb + D < NMH) __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);
+      }
+    }
+  }
+
+  spl += __shfl_xor(spl, 16, 64);
+  spl += __shfl_xor(spl, 32, 64);
+  const int M = args.M, p = args.p;
+  const int i = wbase + lr;
+  if (S == 1) {
+    // rho_i = sum_k sigma_ik sits in the all-ones column PP-1 of the upper half
+    __syncthreads();
+    if (half == 1) xbuf[(size_t)pblk * 64 + lr] = __shfl(G[NMH - 1][3], lr + 48, 64);
+    __syncthreads();
+    const double rho = static_cast<double>(xbuf[(size_t)pblk * 64 + lr]);
+    if (half == 0 && lg == 0 && i < M) args.ll[i] = args.yb[i] - spl;
+    if (i < M) {
+      float *g = reinterpret_cast<float *>(args.g) + static_cast<size_t>(i) * p;
+#pragma unroll
+      for (int mb = 0; mb < NMH; ++mb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = (half * NMH + mb) * 16 + T::crow(lg, v);
+          if (j < p)
+            g[j] = static_cast<float>(args.ytil[j] - (static_cast<double>(G[mb][v]) - args.mu[j] * rho) * args.inv_s[j]);
+        }
+    }
+  } else {
+    const size_t Mp = static_cast<size_t>(args.M_pad);
+    if (half == 0 && lg == 0) args.spl_part[split * Mp + i] = spl;
+    float *gp = reinterpret_cast<float *>(args.g_part) + (split * Mp + i) * PP + half * H;
+#pragma unroll
+    for (int mb = 0; mb < NMH; ++mb) *reinterpret_cast<f32x4 *>(gp + mb * 16 + lg * 4) = G[mb];
+  }
+}
+
 // Sum the S partials of every particle in split order and apply the epilogue.
 template <typename GO, bool GRAD>
 __global__ void gemm_finalize_kernel(GemmArgs args, int PP) {
@@ -640,8 +872,31 @@ static hipError_t launch_one(const GemmArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int PP, bool FP8>
+static hipError_t launch_wide(const GemmArgs &a, hipStream_t s) {
+  constexpr int XS = 32 * (PP * 2 / 16 + 1), TS = PP * (32 * 2 / 16 + 1);
+  constexpr size_t lds = (size_t)(XS + TS) * 16 + 8 * 64 * 8 * sizeof(float);
+  static_assert(lds <= 160 * 1024, "LDS budget of one CU");
+  auto kern = loglik_wide_kernel<PP, FP8>;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int tiles_p = (a.M + 63) / 64;
+  const int g8 = 8 / a.S;
+  const int grid = 8 * ((tiles_p + g8 - 1) / g8);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(512), lds, s, a);
+  return hipGetLastError();
+}
+
 template <Prec P, int PP>
 static hipError_t launch_pp(const GemmArgs &a, hipStream_t s) {
+  if constexpr (P == Prec::BF16X2 && (PP == 384 || PP == 512)) {
+    if (a.grad) return a.x_fp8 ? launch_wide<PP, true>(a, s) : launch_wide<PP, false>(a, s);
+  }
   if constexpr (P == Prec::BF16X2) {
     if (a.x_fp8) {
       if (a.grad) return launch_one<P, PP, true, true>(a, s);

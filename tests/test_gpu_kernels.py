@@ -75,7 +75,7 @@ def test_loglik_fp8_storage_equals_bf16_storage(n, p):
 
 
 @pytest.mark.parametrize("n,p,M", [(2000, 50, 257), (5000, 200, 1000), (334, 127, 130), (1000, 255, 64),
-                                   (130, 63, 129), (64, 100, 200)])
+                                   (130, 63, 129), (64, 100, 200), (400, 300, 130), (1000, 511, 65)])
 def test_grad_fp8_storage_equals_bf16_storage(n, p, M):
     """The BF16 hi+lo log-likelihood with the adjoint from FP8 and from BF16 genotype
     storage (FP8 codes widened to BF16 through registers, BF16 copied straight into LDS):
@@ -170,6 +170,32 @@ def test_grad_parity(name, prec, M, lam):
         assert np.all(err <= tol)
         ltol = 1e-10 if prec == "fp64" else 1e-4
         assert rel_err(lp.cpu().numpy(), lp_ref).max() <= ltol
+
+
+@pytest.mark.parametrize("n,p,xfmt,M", [(400, 300, "bf16", 130), (1000, 500, "fp8", 200), (2000, 383, "fp8", 64),
+                                        (64, 511, "bf16", 70), (130, 450, "bf16", 257), (10000, 500, "fp8", 96)])
+def test_grad_parity_wide_rows(n, p, xfmt, M):
+    """Rows of 384 and 512 markers (the split-marker contraction: two waves per particle
+    block, each with one half of the markers, the forward halves added through LDS), BF16
+    and FP8 genotype storage, ragged individual and particle counts, one and several
+    individual splits: log posterior and gradient against the oracle."""
+    torch = _torch()
+    s, cfg, X, y, Xs = _sampler("n10000_p500_mala_fp8", "bf16x2", n=n, p=p, xfmt=xfmt, move="mala")
+    lam = 0.05
+    b = particles(M, X.shape[1], seed=n + p)
+    bt = torch.from_numpy(b).to("cuda", torch.float32)
+    bs = bt.double().cpu().numpy()
+    g, lp = s.grad(bt, lam)
+    g = g.double().cpu().numpy()
+    ll_ref, gl_ref = likelihood.loglik_and_grad(bs, Xs, y)
+    g_ref = gl_ref + gt_prior.gt_grad(bs, cfg.a, lam)
+    lp_ref = ll_ref + gt_prior.log_prior(bs, cfg.a, lam)
+    tol = _grad_tol("bf16x2", Xs) + 2.0 ** -24 * np.abs(g_ref)
+    err = np.abs(g - g_ref)
+    print(f"n={n} p={p} {xfmt}: grad max abs err {err.max():.3e}, lp max rel err "
+          f"{rel_err(lp.cpu().numpy(), lp_ref).max():.3e}")
+    assert np.all(err <= tol)
+    assert rel_err(lp.cpu().numpy(), lp_ref).max() <= 1e-4
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
