@@ -5,18 +5,20 @@
 // weighted-L1 logistic problem by cyclic coordinate ascent with the curvature bound n/4,
 // beta_j <- S(beta_j + 4 g_j / n, 4 w_j / n), g_j = sum_k (y_k - sigma(eta_k)) X_std,kj.
 //
-// One workgroup (16 wave64s) per start point.  Thread t keeps E_k = exp(-eta_k) and
-// sigma(eta_k) = 1/(1 + E_k) of individuals t, t+1024, ... in registers; the coefficients,
-// the weights and the standardised values of the genotype codes live in LDS.  A column of
-// standardised genotypes takes only three values x_c = (c - mu_j)/s_j, c = 0, 1, 2, so a
-// move beta_j += delta multiplies every E_k by one of the three constants exp(-delta x_c):
-// one exponential per lane (lane l computes the one of code l mod 4; code 3 marks padded
-// individuals, x = 0) broadcast by a lane shuffle, then per individual one multiply and a
-// reciprocal (hardware estimate refined by two Newton steps).  The columns are read as
+// One workgroup (8 wave64s, two per SIMD) per start point.  Thread t keeps E_k = exp(-eta_k)
+// and sigma(eta_k) = 1/(1 + E_k) of individuals t, t+512, ... in registers; the
+// coefficients, the weights and the standardised values of the genotype codes live in LDS.
+// A column of standardised genotypes takes only three values x_c = (c - mu_j)/s_j, c = 0,
+// 1, 2, so a move beta_j += delta multiplies every E_k by one of the three constants
+// exp(-delta x_c): lanes 0..3 of each wave put them (and 1 for code 3, padded individuals)
+// in a four-entry table in LDS, then per individual one table read, one multiply and a
+// reciprocal (hardware estimate refined by one Newton step).  The columns are read as
 // one-byte codes.  As in the oracle, eta is recomputed from the coefficients at the start
 // of every coordinate sweep, which also bounds the rounding of the products to one sweep.
-// Each coordinate update is one block-wide reduction of g_j (wave sums, then the 16 wave
-// partials added in a fixed order by every thread, so all threads take the same value).
+// Each coordinate update is one block-wide reduction of g_j (a DPP sum inside each wave,
+// then the 8 wave partials added as a fixed tree by every thread, so all threads take the
+// same value).  A coordinate update is latency-bound: at n = 5000 it is ~4000 cycles, most
+// of it the per-individual FP64 work of the waves sharing a SIMD and the barrier.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -27,25 +29,55 @@ namespace spa {
 
 namespace {
 
-constexpr int kMapThreads = 1024;
+constexpr int kMapThreads = 512;
 constexpr int kMapWaves = kMapThreads / 64;
 
-// 1 / (1 + e) for e >= 0 (e = +inf gives 0): hardware reciprocal and two Newton steps.
+// DPP move of a double (two 32-bit moves); lanes of rows outside ROWS read 0.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned in every lane: butterflies
+// inside each row of 16 lanes (quad permutations, half-row and row mirrors), the row totals
+// chained by the row-15 and row-31 broadcasts, the total read from lane 63.  Six dependent
+// DPP steps instead of six dependent cross-lane permutes through the LDS unit.
+__device__ __forceinline__ double wave_total(double v) {
+  v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x141>(v);       // row_half_mirror
+  v += dpp_f64<0x140>(v);       // row_mirror
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return readlane_f64(v, 63);
+}
+
+// 1 / (1 + e) for e >= 0 (e = +inf gives 0): hardware reciprocal (relative error near
+// 2^-23) and one Newton step (error near 2^-46, squared by the step).
 __device__ __forceinline__ double inv1p(double e) {
   const double d = 1.0 + e;
   if (!(d < INFINITY)) return 0.0;
   double r = __builtin_amdgcn_rcp(d);
-  double q = fma(-d, r, 1.0);
-  r = fma(r, q, r);
-  q = fma(-d, r, 1.0);
+  const double q = fma(-d, r, 1.0);
   return fma(r, q, r);
 }
 
 template <typename IT, int R>
 __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
   __shared__ double bl[kMapMaxP], wl[kMapMaxP], xv[kMapMaxP][4];
-  __shared__ double part[2][kMapWaves];
+  __shared__ __align__(16) double part[2][kMapWaves];
   __shared__ double red[kMapWaves];
+  __shared__ double cltab[kMapWaves][4];   // per wave: exp(-delta x_c) of codes 0..3
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int s = blockIdx.x;                      // start point
   const int n = a.n, n_pad = a.n_pad, p = a.p;
@@ -116,21 +148,32 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
         double g = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) g += (yk[r] - sg[r]) * xv[j][c[r]];   // padded: x = 0
-        g = wave_sum(g);
+        g = wave_total(g);
         if (lane == 0) part[parity][wave] = g;
         __syncthreads();
-        g = part[parity][0];
+        {
+          // the wave sums, added as a balanced tree (the same order in every thread)
+          static_assert(kMapWaves == 8, "tree of 8 wave sums");
+          const double2 *pp = reinterpret_cast<const double2 *>(part[parity]);
+          double t[4];
 #pragma unroll
-        for (int w = 1; w < kMapWaves; ++w) g += part[parity][w];
+          for (int i = 0; i < 4; ++i) {
+            const double2 q = pp[i];
+            t[i] = q.x + q.y;
+          }
+          g = (t[0] + t[1]) + (t[2] + t[3]);
+        }
         parity ^= 1;
         const double z = bj + inv_n4 * g, thr = inv_n4 * wj;
         const double nb = z > thr ? z - thr : (z < -thr ? z + thr : 0.0);
         const double delta = nb - bj;
         if (delta != 0.0) {                      // uniform: every thread holds the same values
-          const double cl = exp(-delta * xv[j][lane & 3]);   // lanes 0..3 hold codes 0..3
+          // lanes 0..3 put the factor of codes 0..3 in the wave's table (x_3 = 0: factor 1);
+          // the wave's LDS accesses are processed in order, so its reads see the new table
+          if (lane < 4) cltab[wave][lane] = exp(-delta * xv[j][lane]);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            E[r] *= __shfl(cl, c[r], 64);
+            E[r] *= cltab[wave][c[r]];
             sg[r] = inv1p(E[r]);
           }
         }
@@ -248,13 +291,16 @@ hipError_t launch_em_t(const MapArgs &a, hipStream_t st) {
   else if (R <= 6) launch_em_r<IT, 6>(a, st);
   else if (R <= 8) launch_em_r<IT, 8>(a, st);
   else if (R <= 10) launch_em_r<IT, 10>(a, st);
+  else if (R <= 12) launch_em_r<IT, 12>(a, st);
+  else if (R <= 16) launch_em_r<IT, 16>(a, st);
+  else if (R <= 20) launch_em_r<IT, 20>(a, st);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 }  // namespace
 
-int map_max_n() { return kMapThreads * 10; }
+int map_max_n() { return kMapThreads * 20; }
 
 hipError_t launch_map_cols(const uint8_t *X, const uint8_t *y, int n, int p, int n_pad, const double *mu,
                            const double *sd, uint8_t *codes, double *xv, double *yv, hipStream_t st) {
