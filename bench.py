@@ -78,11 +78,17 @@ def copy_calibration():
     print(f"copied 3 x {n * 4} bytes", flush=True)
 
 
-# VALU issue slots per eta-element update of the FP32 single-coordinate kernel (its ISA:
-# 141 VALU + 17 transcendental instructions per coordinate update of 8 individuals per
-# lane, a transcendental taking four slots), and the chip's VALU lane-slot rate:
-# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 vector peak counts an
-# FMA as two flops and packed FP32 as two lanes).
+# The single-coordinate kernel's roofline is taken on the method's own work per
+# eta-element update (particle i, coordinate j, individual k), not on the kernel's
+# instructions: the update eta' = eta + delta x (one FMA), the new e^-|eta'| (one
+# exponential, a quarter-rate instruction: four lane-slots), its factor in the
+# likelihood-ratio product (one multiply-add) and the linear term y delta x (one
+# multiply-add): 3 + 4 = 7 VALU lane-slots.  The chip's VALU lane-slot rate is
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 vector peak counts an FMA
+# as two flops and packed FP32 as two lanes).  For comparison the kernel itself issues 141
+# VALU + 17 transcendental instructions per coordinate update of 8 individuals per lane
+# (its ISA), 26.1 lane-slots per element update; the ratio of the two is its overhead.
+SINGLE_SITE_ALG_SLOTS = 3 + 4 * 1
 SINGLE_SITE_SLOTS = (141 + 4 * 17) / 8.0
 VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 
@@ -116,9 +122,12 @@ def single_site_leg(steps: int = 10):
             "ms_per_step": round(el * 1e3, 4), "kernel_ms_per_step": round(k_s * 1e3, 4),
             "eta_updates_per_s": round(units / el, 1), "kernel_eta_updates_per_s": round(rate_k, 1),
             "est_full_run_s_T450": round(el * (cfg.T - 1), 2),
-            "roofline": {"bound": "alu", "achieved": round(rate_k * SINGLE_SITE_SLOTS / 1e12, 3),
+            "roofline": {"bound": "alu", "achieved": round(rate_k * SINGLE_SITE_ALG_SLOTS / 1e12, 3),
                          "peak": round(VALU_LANE_SLOTS_PER_S / 1e12, 3), "unit": "T VALU lane-slots/s",
-                         "frac": round(rate_k * SINGLE_SITE_SLOTS / VALU_LANE_SLOTS_PER_S, 4)}}
+                         "frac": round(rate_k * SINGLE_SITE_ALG_SLOTS / VALU_LANE_SLOTS_PER_S, 4),
+                         "slots_per_update": SINGLE_SITE_ALG_SLOTS,
+                         "kernel_slots_per_update": round(SINGLE_SITE_SLOTS, 2),
+                         "issue_frac": round(rate_k * SINGLE_SITE_SLOTS / VALU_LANE_SLOTS_PER_S, 4)}}
 
 
 def analysis_legs(torch, s, cfg):
