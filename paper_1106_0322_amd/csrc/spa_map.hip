@@ -169,8 +169,10 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
         const double delta = nb - bj;
         if (delta != 0.0) {                      // uniform: every thread holds the same values
           // lanes 0..3 put the factor of codes 0..3 in the wave's table (x_3 = 0: factor 1);
-          // the wave's LDS accesses are processed in order, so its reads see the new table
+          // a wave's LDS accesses are processed in order, and the wave barrier keeps the
+          // compiler from moving the table reads above the write
           if (lane < 4) cltab[wave][lane] = exp(-delta * xv[j][lane]);
+          __builtin_amdgcn_wave_barrier();
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             E[r] *= cltab[wave][c[r]];
