@@ -153,6 +153,7 @@ struct spa_smc {
   double *map_starts = nullptr, *map_modes = nullptr, *map_mlp = nullptr;
   // single-coordinate kernel operands (standardised genotype columns, labels)
   void *xs_ss = nullptr, *yv_ss = nullptr;
+  float *cs_ss = nullptr;   // FP32: column coefficients sum_k (y_k - 1/2) xs_jk
   // sparsity-path summaries (per scale, and the c-marginal mixture)
   SqLevels sq_lv{};
   bool sq_on = false, sq_keep = false;
@@ -617,6 +618,7 @@ spa_status single_site_cycles(spa_smc *h, int t, int cycles, double lam) {
   SingleSiteArgs a{};
   a.xs = h->xs_ss;
   a.yv = h->yv_ss;
+  a.cs = h->cs_ss;
   a.beta = h->beta;
   a.ll = h->ll;
   a.acc_cnt = h->acc;
@@ -995,6 +997,15 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
       return fail(SPA_ERR_HIP);
     }
     launch_labels(h->dy, n, h->n_pad, h->f64, h->yv_ss, h->stream);
+    if (!h->f64) {
+      if ((st = dalloc(h, &h->cs_ss, sizeof(float) * (size_t)p)) != SPA_OK) return fail(st);
+      he = launch_lin_cols(static_cast<const float *>(h->xs_ss), static_cast<const float *>(h->yv_ss), n, p,
+                           h->n_pad, h->cs_ss, h->stream);
+      if (he != hipSuccess) {
+        hip_fail(h, he, "lin_cols");
+        return fail(SPA_ERR_HIP);
+      }
+    }
   }
 
   // ---- initial particles: beta = 0, burn-in targeting pi_1, equal weights

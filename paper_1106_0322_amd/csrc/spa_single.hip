@@ -7,11 +7,21 @@
 // standardised genotype column (contiguous bytes per lane group), forms the likelihood
 // difference with one exponential per individual (the cached e^{-|eta|} gives the other
 // softplus term) and one logarithm per lane (the ratio terms are multiplied first), and
-// reduces it across the wave.  The particle's coefficients are held by lane j mod 64 and
+// reduces it across the wave.
+//
+// The FP32 instance uses softplus(z) = z/2 + |z|/2 + log(1 + e^{-|z|}): with d_k = delta x_k
+// the likelihood difference of a move is
+//   delta c_j + (1/2) sum_k (|eta_k| - |eta_k + d_k|) + log(prod_k (1 + e^{-|eta_k|}) / prod_k (1 + e^{-|eta_k + d_k|})),
+// c_j = sum_k (y_k - 1/2) x_kj one number per column, sum_k |eta_k| kept per lane (replaced
+// on acceptance), the two products accumulated with FMAs and divided once per lane; eta is
+// kept in log2 units so that e^{-|eta|} is one exp2.  Per individual and move: one FMA for
+// the new eta, one exponential, two FMAs for the products and one add.  The particle's coefficients are held by lane j mod 64 and
 // broadcast with readlane; the cycle's normals and uniforms are drawn up front, one
 // Philox block per coordinate, by the lane holding that coordinate.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "spa_common.hpp"
 #include "spa_single.hpp"
@@ -46,6 +56,23 @@ __device__ __forceinline__ float wave_sum_t(float v) {
   return v;
 }
 __device__ __forceinline__ double wave_sum_t(double v) { return wave_sum(v); }
+
+// FP32 sum over the 64 lanes, the same value in every lane: butterflies inside each row of
+// 16 lanes by DPP moves (quad permutations, half-row and row mirrors), the row totals
+// chained by the row-15 and row-31 broadcasts, the total read from lane 63.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
+}
+__device__ __forceinline__ float wave_total_f32(float v) {
+  v += dpp_f32<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f32<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f32<0x141>(v);       // row_half_mirror
+  v += dpp_f32<0x140>(v);       // row_mirror
+  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
 
 // log u and log Gt(b') - log Gt(b) in the particle precision (FP64: the oracle's
 // arithmetic, so the decisions match it; FP32: one logarithm of a ratio each).
@@ -115,10 +142,78 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
       }
     }
   }
+  int cnt = 0;
+  if constexpr (std::is_same<PT, float>::value) {
+    constexpr float kL2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
+    float sa = 0.0f;   // this lane's sum of |eta| (log2 units)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      eta[r] *= kL2e;
+      em[r] = __builtin_amdgcn_exp2f(-fabsf(eta[r]));
+      sa += fabsf(eta[r]);
+    }
+    for (int c = 0; c < a.cycles; ++c) {
+      const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
+      float zv[kMaxCoordBlocks];
+      uint32_t uw[kMaxCoordBlocks];
+#pragma unroll
+      for (int m = 0; m < kMaxCoordBlocks; ++m) {
+        const int j = lane + 64 * m;
+        zv[m] = 0.0f;
+        uw[m] = 0u;
+        if (64 * m < p && j < p) {
+          const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j), cyc,
+                                                   word3(a.t, kTagSingleSite)),
+                                        a.k0, a.k1);
+          zv[m] = draw_normal(w, 0.0f);
+          uw[m] = w.z;
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxCoordBlocks; ++m) {
+        if (64 * m >= p) break;
+        for (int jl = 0; jl < 64 && 64 * m + jl < p; ++jl) {
+          const int j = 64 * m + jl;
+          const float delta = step * bcast(zv[m], jl);
+          const float dl = delta * kL2e;
+          const PT *col = xs + (size_t)j * n_pad;
+          float e1[R], en[R];
+          float num = 1.0f, den = 1.0f, sn = 0.0f;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int k = lane + 64 * r;
+            const float x = k < n_pad ? col[k] : 0.0f;
+            e1[r] = fmaf(dl, x, eta[r]);
+            en[r] = __builtin_amdgcn_exp2f(-fabsf(e1[r]));
+            num = fmaf(num, em[r], num);
+            den = fmaf(den, en[r], den);
+            sn += fabsf(e1[r]);
+          }
+          const float part = kLn2 * (0.5f * (sa - sn) + __builtin_amdgcn_logf(num * __builtin_amdgcn_rcpf(den)));
+          const float dll = wave_total_f32(part) + delta * a.cs[j];
+          const float bj = bcast(bv[m], jl);
+          const float bn = bj + delta;
+          const float dlp = prior_diff(bn, bj, pr);
+          const uint32_t w2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(uw[m]), jl));
+          if (log_uniform(w2, 0.0f) < dll + dlp) {   // uniform across the wave (lane-identical sums)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              eta[r] = e1[r];
+              em[r] = en[r];
+            }
+            sa = sn;
+            if (lane == jl) bv[m] = bn;
+            ++cnt;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) eta[r] *= kLn2;   // back to natural units for the write-back
+  } else {
 #pragma unroll
   for (int r = 0; r < R; ++r) em[r] = exp_neg(fabs(eta[r]));
 
-  int cnt = 0;
   for (int c = 0; c < a.cycles; ++c) {
     const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
     PT zv[kMaxCoordBlocks];
@@ -173,6 +268,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
       }
     }
   }
+  }
 
   // write back: coefficients, log-likelihood from the tracked predictor, accept count
 #pragma unroll
@@ -210,6 +306,17 @@ __global__ void std_cols_kernel(const uint8_t *__restrict__ X, int n, int p, int
   }
 }
 
+// c_j = sum_{k < n} (y_k - 1/2) xs_jk: one wave per column, FP64 sums of the FP32 values.
+__global__ __launch_bounds__(64) void lin_cols_kernel(const float *__restrict__ xs, const float *__restrict__ yv,
+                                                     int n, int n_pad, float *__restrict__ cs) {
+  const int j = blockIdx.x, lane = threadIdx.x;
+  double acc = 0.0;
+  for (int k = lane; k < n; k += 64)
+    acc += (static_cast<double>(yv[k]) - 0.5) * static_cast<double>(xs[(size_t)j * n_pad + k]);
+  acc = wave_sum(acc);
+  if (lane == 0) cs[j] = static_cast<float>(acc);
+}
+
 template <typename PT, int R>
 static void launch_r(const SingleSiteArgs &a, hipStream_t st) {
   hipLaunchKernelGGL((single_site_kernel<PT, R>), dim3((a.M + 3) / 4), dim3(256), 0, st, a);
@@ -245,6 +352,11 @@ hipError_t launch_std_cols(bool f64, const uint8_t *X, int n, int p, int n_pad, 
   else
     hipLaunchKernelGGL(std_cols_kernel<float>, dim3(grid), dim3(256), 0, st, X, n, p, n_pad, mu, s,
                        reinterpret_cast<float *>(xs));
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_cols(const float *xs, const float *yv, int n, int p, int n_pad, float *cs, hipStream_t st) {
+  hipLaunchKernelGGL(lin_cols_kernel, dim3(p), dim3(64), 0, st, xs, yv, n, n_pad, cs);
   return hipGetLastError();
 }
 

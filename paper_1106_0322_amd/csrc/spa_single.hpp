@@ -11,6 +11,7 @@ namespace spa {
 struct SingleSiteArgs {
   const void *xs;       // p x n_pad standardised genotypes, particle precision, zero padded
   const void *yv;       // n_pad labels, particle precision, zero padded
+  const float *cs;      // FP32 instance: p column coefficients c_j = sum_k (y_k - 1/2) xs_jk
   void *beta;           // M x p particles (updated in place)
   double *ll;           // M log-likelihoods (output, from the tracked linear predictor)
   int *acc_cnt;         // M accepted coordinate updates (accumulated)
@@ -27,5 +28,7 @@ int single_site_max_n();
 hipError_t launch_single_site(bool f64, const SingleSiteArgs &a, hipStream_t st);
 hipError_t launch_std_cols(bool f64, const uint8_t *X, int n, int p, int n_pad, const double *mu,
                            const double *s, void *xs, hipStream_t st);
+// c_j = sum_{k < n} (y_k - 1/2) xs_jk from the FP32 columns and labels (FP64 sums, FP32 out).
+hipError_t launch_lin_cols(const float *xs, const float *yv, int n, int p, int n_pad, float *cs, hipStream_t st);
 
 }  // namespace spa
