@@ -246,7 +246,7 @@ def gemm_flops(cfg) -> float:
     return f * (2.0 if cfg.move == "mala" else 1.0)
 
 
-def cpu_leg(workload: str, N: int = 1024, init_sweeps: int = 4, steps: int = 2) -> dict:
+def cpu_leg(workload: str, N: int = 1024, init_sweeps: int = 4, steps: int = 8) -> dict:
     """The oracle (FP64 NumPy, untuned) running the sampler itself on the workload's data:
     burn-in and the first scale steps of a whole SMC sweep at N particles, timed on this
     process's threads.  Returns the algorithmic contraction throughput (the GPU line's
