@@ -68,7 +68,7 @@ __global__ void fp8x_pack_x_kernel(const uint8_t *__restrict__ X, int n, int p, 
   }
 }
 
-// Reductions over the LN lanes of a particle (fixed xor-butterfly order).
+// Reductions over the LN lanes of a particle (fixed orders).
 template <int LN>
 __device__ __forceinline__ double f8_group_max(double v) {
 #pragma unroll
@@ -77,9 +77,7 @@ __device__ __forceinline__ double f8_group_max(double v) {
 }
 template <int LN>
 __device__ __forceinline__ double f8_group_sum(double v) {
-#pragma unroll
-  for (int o = LN / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return lane_group_sum<LN>(v);   // the order of the proposal step's sums (bit-identical operands)
 }
 template <int LN>
 __device__ __forceinline__ int f8_group_or(int v) {

@@ -242,13 +242,11 @@ __device__ __forceinline__ void store4(T *dst, bool vec, int j0, int lim, const 
 // 4LP+4l..4LP+4l+3 (one Philox block of four normals each), which covers p <= 8 LP - 1.
 constexpr int kRowBlocks = 2;
 
-// Sum over the LP lanes of a particle (fixed xor-butterfly order; the same value in every
-// lane of the group).
+// Sum over the LP lanes of a particle, the same value in every lane of the group (the
+// butterfly of lane_group_sum; the FP8 operand packing sums in the same order).
 template <int LP>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = LP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  return lane_group_sum<LP>(v);
 }
 
 template <int LP>
