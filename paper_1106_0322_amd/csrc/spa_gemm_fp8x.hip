@@ -43,6 +43,7 @@
 // the row's 16-byte chunks 4*0+g and 4*1+g of the step.  The E8M0 scale of each operand is
 // byte 0 of a per-lane register; every lane of a column carries the same exponent.
 #include "spa_common.hpp"
+#include "spa_lanes.hpp"
 #include "spa_gemm_fp8x.hpp"
 #include "spa_internal.hpp"
 

@@ -3,6 +3,7 @@
 // moments.  Row kernels map one wave64 to one particle (its p coefficients are contiguous,
 // so a wave reads a row with 16-byte lanes); reductions use fixed butterfly/tree orders.
 #include "spa_common.hpp"
+#include "spa_lanes.hpp"
 #include "spa_kernels.hpp"
 
 namespace spa {

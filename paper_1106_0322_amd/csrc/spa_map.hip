@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include "spa_common.hpp"
+#include "spa_lanes.hpp"
 #include "spa_map.hpp"
 
 namespace spa {
@@ -31,36 +32,6 @@ namespace {
 
 constexpr int kMapThreads = 512;
 constexpr int kMapWaves = kMapThreads / 64;
-
-// DPP move of a double (two 32-bit moves); lanes of rows outside ROWS read 0.
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWS, 0xf, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
-  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
-// Sum over the 64 lanes of a wave in a fixed order, returned in every lane: butterflies
-// inside each row of 16 lanes (quad permutations, half-row and row mirrors), the row totals
-// chained by the row-15 and row-31 broadcasts, the total read from lane 63.  Six dependent
-// DPP steps instead of six dependent cross-lane permutes through the LDS unit.
-__device__ __forceinline__ double wave_total(double v) {
-  v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp_f64<0x141>(v);       // row_half_mirror
-  v += dpp_f64<0x140>(v);       // row_mirror
-  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return readlane_f64(v, 63);
-}
 
 // 1 / (1 + e) for e >= 0 (e = +inf gives 0): hardware reciprocal (relative error near
 // 2^-23) and one Newton step (error near 2^-46, squared by the step).
@@ -148,7 +119,7 @@ __global__ __launch_bounds__(kMapThreads) void map_em_kernel(MapArgs a) {
         double g = 0.0;
 #pragma unroll
         for (int r = 0; r < R; ++r) g += (yk[r] - sg[r]) * xv[j][c[r]];   // padded: x = 0
-        g = wave_total(g);
+        g = wave_total_f64(g);
         if (lane == 0) part[parity][wave] = g;
         __syncthreads();
         {

@@ -24,6 +24,7 @@
 #include <type_traits>
 
 #include "spa_common.hpp"
+#include "spa_lanes.hpp"
 #include "spa_single.hpp"
 
 namespace spa {
@@ -56,23 +57,6 @@ __device__ __forceinline__ float wave_sum_t(float v) {
   return v;
 }
 __device__ __forceinline__ double wave_sum_t(double v) { return wave_sum(v); }
-
-// FP32 sum over the 64 lanes, the same value in every lane: butterflies inside each row of
-// 16 lanes by DPP moves (quad permutations, half-row and row mirrors), the row totals
-// chained by the row-15 and row-31 broadcasts, the total read from lane 63.
-template <int CTRL, int ROWS = 0xf>
-__device__ __forceinline__ float dpp_f32(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, false));
-}
-__device__ __forceinline__ float wave_total_f32(float v) {
-  v += dpp_f32<0xB1>(v);        // quad_perm [1,0,3,2]
-  v += dpp_f32<0x4E>(v);        // quad_perm [2,3,0,1]
-  v += dpp_f32<0x141>(v);       // row_half_mirror
-  v += dpp_f32<0x140>(v);       // row_mirror
-  v += dpp_f32<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_f32<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
-}
 
 // log u and log Gt(b') - log Gt(b) in the particle precision (FP64: the oracle's
 // arithmetic, so the decisions match it; FP32: one logarithm of a ratio each).
