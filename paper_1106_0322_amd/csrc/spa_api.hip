@@ -577,7 +577,7 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   ProposeArgs na = pa;
   na.sweep = static_cast<uint32_t>(s + 1);
   tbeg(h, SPA_T_ACCEPT);
-  launch_accept(h->prec, mala, h->PP, aa, make_next ? &na : nullptr, h->stream);
+  SPA_CK(h, launch_accept(h->prec, mala, h->PP, aa, make_next ? &na : nullptr, h->stream));
   tend(h);
   SPA_CK(h, hipGetLastError());
   return SPA_OK;

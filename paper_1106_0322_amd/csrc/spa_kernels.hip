@@ -484,13 +484,18 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
 }
 
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
-// PARTS: the proposal's log-likelihood and likelihood gradient are combined from the split
-// contraction's partial sums.  NEXT: the wave then draws the next sweep's proposal from
-// the row it has just decided (the state after this decision, still in registers), so the
-// next sweep needs no separate proposal launch; valid while the proposal scale, the step
-// size and the prior stay fixed between the two sweeps.
-template <Prec P, typename PT, bool MALA, bool PARTS, bool NEXT, int LP, bool F8>
+// SPL > 0: the proposal's log-likelihood and likelihood gradient are combined from the SPL
+// partial sums of the split contraction (a compile-time count, so that every partial is
+// loaded at once rather than one memory round trip per split).  NEXT: the wave then draws
+// the next sweep's proposal from the row it has just decided (the state after this
+// decision, still in registers), so the next sweep needs no separate proposal launch;
+// valid while the proposal scale, the step size and the prior stay fixed between the two
+// sweeps.  The current gradient row is read with the other rows at the start, for every
+// particle (a rejected row needs it for its next proposal), so that no row load waits on
+// the decision.
+template <Prec P, typename PT, bool MALA, int SPL, bool NEXT, int LP, bool F8>
 __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs na) {
+  constexpr bool PARTS = SPL > 0;
   const int lane = threadIdx.x & (LP - 1);
   const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
   if (i >= a.M) return;
@@ -499,18 +504,22 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
   PT *gl = reinterpret_cast<PT *>(a.gl) + (size_t)i * p;
   const Prior pr = a.prior;
   PT nv[kRowBlocks][4], cur[kRowBlocks][4], gnew[kRowBlocks][4];
+  PT gold[(MALA && NEXT) ? kRowBlocks : 1][4];
   load_row<LP>(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
   load_row<LP>(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
+  if constexpr (MALA && NEXT) load_row<LP>(const_cast<const PT *>(gl), lane, p, gold);
   double llp;
   if constexpr (PARTS) {
     double spl = 0.0;
-    for (int s = 0; s < a.S; ++s) spl += a.spl_part[s * a.Mp + i];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) spl += a.spl_part[s * a.Mp + i];
     llp = a.yb[i] - spl;
     if constexpr (MALA) {
       const PT *gp = reinterpret_cast<const PT *>(a.g_part);
       const int PP = a.PP;
       double rho = 0.0;
-      for (int s = 0; s < a.S; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * PP + PP - 1]);
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) rho += static_cast<double>(gp[(s * a.Mp + i) * PP + PP - 1]);
 #pragma unroll
       for (int kb = 0; kb < kRowBlocks; ++kb) {
         const int b0 = lane * 4 + 4 * LP * kb;
@@ -518,7 +527,8 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
         for (int k = 0; k < 4; ++k) gnew[kb][k] = PT(0);
         if (b0 >= p) continue;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int s = 0; s < a.S; ++s) {   // rows are PP long, PP a multiple of 32: aligned blocks
+#pragma unroll
+        for (int s = 0; s < SPL; ++s) {   // rows are PP long, PP a multiple of 32: aligned blocks
           PT t4[4];
           load4(gp + (s * a.Mp + i) * PP, true, b0, PP, t4);
 #pragma unroll
@@ -562,6 +572,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
     lqr = -group_sum<LP>(static_cast<double>(q));
   }
   const double log_alpha = llp - a.ll[i] + a.lp_prop[i] - a.lp_cur[i] + lqr - a.lqf[i];
+  const int cnt = a.acc_cnt[i];
   const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), 0u, a.sweep, word3(a.t, kTagUniform)),
                                 a.k0, a.k1);
   const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
@@ -571,31 +582,18 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
     if constexpr (MALA) store_row<LP>(gl, lane, p, gnew);
     if (lane == 0) a.ll[i] = llp;
   }
-  if (lane == 0) a.acc_cnt[i] += acc ? 1 : 0;
+  if (lane == 0) a.acc_cnt[i] = cnt + (acc ? 1 : 0);
   if constexpr (NEXT) {
-    PT gv[kRowBlocks][4];
-    if constexpr (MALA) {
-      if (acc) {
+    PT nc[kRowBlocks][4], gv[kRowBlocks][4];
 #pragma unroll
-        for (int kb = 0; kb < kRowBlocks; ++kb)
+    for (int kb = 0; kb < kRowBlocks; ++kb)
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            cur[kb][k] = nv[kb][k];
-            gv[kb][k] = gnew[kb][k];
-          }
-      } else {
-        load_row<LP>(const_cast<const PT *>(gl), lane, p, gv);
+      for (int k = 0; k < 4; ++k) {
+        nc[kb][k] = acc ? nv[kb][k] : cur[kb][k];
+        if constexpr (MALA) gv[kb][k] = acc ? gnew[kb][k] : gold[kb][k];
+        else gv[kb][k] = PT(0);
       }
-    } else {
-#pragma unroll
-      for (int kb = 0; kb < kRowBlocks; ++kb)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (acc) cur[kb][k] = nv[kb][k];
-          gv[kb][k] = PT(0);
-        }
-    }
-    propose_row<P, PT, MALA, LP, F8>(na, i, lane, true, cur, gv);
+    propose_row<P, PT, MALA, LP, F8>(na, i, lane, true, nc, gv);
   }
 }
 
@@ -1239,43 +1237,50 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) 
   }
 }
 
-template <Prec P, typename PT, bool MALA, bool NEXT, bool F8 = false>
-static void launch_accept_t(bool parts, int PP, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
-  if (row_lanes(PP) == 32) {
-    const int grid = grid_rows(a.M, 8);
-    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 32, F8>), dim3(grid), dim3(256), 0, st, a, na);
-    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 32, F8>), dim3(grid), dim3(256), 0, st, a, na);
-  } else {
-    const int grid = grid_rows(a.M, 4);
-    if (parts) hipLaunchKernelGGL((accept_kernel<P, PT, MALA, true, NEXT, 64, F8>), dim3(grid), dim3(256), 0, st, a, na);
-    else hipLaunchKernelGGL((accept_kernel<P, PT, MALA, false, NEXT, 64, F8>), dim3(grid), dim3(256), 0, st, a, na);
+template <Prec P, typename PT, bool MALA, bool NEXT, int LP, bool F8>
+static void launch_accept_lp(int S, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
+  const int grid = grid_rows(a.M, 256 / LP);
+  switch (S) {
+    case 1: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 0, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 2: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 2, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 4: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 4, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 8: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 8, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
   }
 }
 
+// S: the number of partial sums to combine (1: the contraction wrote whole results).
+template <Prec P, typename PT, bool MALA, bool NEXT, bool F8 = false>
+static void launch_accept_t(int S, int PP, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
+  if (row_lanes(PP) == 32) launch_accept_lp<P, PT, MALA, NEXT, 32, F8>(S, a, na, st);
+  else launch_accept_lp<P, PT, MALA, NEXT, 64, F8>(S, a, na, st);
+}
+
 template <Prec P, typename PT>
-static void launch_accept_p(bool mala, bool parts, int PP, const AcceptArgs &a, const ProposeArgs *next,
+static void launch_accept_p(bool mala, int S, int PP, const AcceptArgs &a, const ProposeArgs *next,
                             hipStream_t st) {
   const ProposeArgs none{};
   if (next) {
     if constexpr (P == Prec::BF16X2) {
       if (!mala && next->f8_terms > 0) {
-        launch_accept_t<P, PT, false, true, true>(parts, PP, a, *next, st);
+        launch_accept_t<P, PT, false, true, true>(S, PP, a, *next, st);
         return;
       }
     }
-    if (mala) launch_accept_t<P, PT, true, true>(parts, PP, a, *next, st);
-    else launch_accept_t<P, PT, false, true>(parts, PP, a, *next, st);
+    if (mala) launch_accept_t<P, PT, true, true>(S, PP, a, *next, st);
+    else launch_accept_t<P, PT, false, true>(S, PP, a, *next, st);
   } else {
-    if (mala) launch_accept_t<P, PT, true, false>(parts, PP, a, none, st);
-    else launch_accept_t<P, PT, false, false>(parts, PP, a, none, st);
+    if (mala) launch_accept_t<P, PT, true, false>(S, PP, a, none, st);
+    else launch_accept_t<P, PT, false, false>(S, PP, a, none, st);
   }
 }
 
-void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
-  const bool parts = a.spl_part != nullptr;
-  if (prec == Prec::F64) launch_accept_p<Prec::F64, double>(mala, parts, PP, a, next, st);
-  else if (prec == Prec::F32 || !next) launch_accept_p<Prec::F32, float>(mala, parts, PP, a, next, st);
-  else launch_accept_p<Prec::BF16X2, float>(mala, parts, PP, a, next, st);   // no operand written: one instance
+hipError_t launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st) {
+  const int S = a.spl_part != nullptr ? a.S : 1;
+  if (S != 1 && S != 2 && S != 4 && S != 8) return hipErrorInvalidValue;   // split counts are powers of two <= 8
+  if (prec == Prec::F64) launch_accept_p<Prec::F64, double>(mala, S, PP, a, next, st);
+  else if (prec == Prec::F32 || !next) launch_accept_p<Prec::F32, float>(mala, S, PP, a, next, st);
+  else launch_accept_p<Prec::BF16X2, float>(mala, S, PP, a, next, st);   // no operand written: one instance
+  return hipSuccess;
 }
 
 int reweight_blocks(int M, int p) {

@@ -106,7 +106,7 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st);
 // next != null: the decision kernel also draws the next sweep's proposal (same buffers as
 // a launch_propose with *next) from each row it has just decided.  PP: the padded row
 // length of the contraction's operand (it sets the lanes per particle row).
-void launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st);
+hipError_t launch_accept(Prec prec, bool mala, int PP, const AcceptArgs &a, const ProposeArgs *next, hipStream_t st);
 // Workgroups of the reweighting pass (its partials hold 3 doubles per workgroup); the
 // launch is the pass and the one-workgroup combination of its partials.
 int reweight_blocks(int M, int p);
