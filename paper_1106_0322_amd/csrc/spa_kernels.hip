@@ -238,6 +238,37 @@ __device__ __forceinline__ void store4(T *dst, bool vec, int j0, int lim, const 
   }
 }
 
+// One aligned vector access of the block of four at j0.
+template <typename T>
+__device__ __forceinline__ void vload4(const T *src, int j0, T out[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4 *>(src + j0);
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+  } else {
+    const f64x4 v = *reinterpret_cast<const f64x4 *>(src + j0);
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+  }
+}
+template <typename T>
+__device__ __forceinline__ void vstore4(T *dst, int j0, const T v[4]) {
+  if constexpr (sizeof(T) == 4) *reinterpret_cast<float4 *>(dst + j0) = make_float4(v[0], v[1], v[2], v[3]);
+  else *reinterpret_cast<f64x4 *>(dst + j0) = f64x4{v[0], v[1], v[2], v[3]};
+}
+// load4 / store4 of a block that starts inside the array (j0 < lim, which the caller
+// guarantees).  VR: lim is a multiple of 4 and the blocks are aligned, so the block is
+// whole: one vector access with no checks (the checks' branches kept the compiler from
+// issuing a row's loads together).
+template <bool VR, typename T>
+__device__ __forceinline__ void load4in(const T *src, bool vec, int j0, int lim, T out[4]) {
+  if constexpr (VR) vload4(src, j0, out);
+  else load4(src, vec, j0, lim, out);
+}
+template <bool VR, typename T>
+__device__ __forceinline__ void store4in(T *dst, bool vec, int j0, int lim, const T v[4]) {
+  if constexpr (VR) vstore4(dst, j0, v);
+  else store4(dst, vec, j0, lim, v);
+}
+
 // Particle rows in registers: LP lanes per particle (64, or 32 for rows of at most 256
 // markers, two particles per wave); sub-lane l holds markers 4l..4l+3 and
 // 4LP+4l..4LP+4l+3 (one Philox block of four normals each), which covers p <= 8 LP - 1.
@@ -311,7 +342,7 @@ __device__ __forceinline__ void f8_terms_row(const ProposeArgs &a, const int i, 
 // get a zero operand row.
 // F8: the instance for random-walk rows of a handle on the FP8 multi-term contraction
 // (compiled separately, so the other instances keep their register budget).
-template <Prec P, typename PT, bool MALA, int LP, bool F8 = false>
+template <Prec P, typename PT, bool MALA, int LP, bool F8, bool VR>
 __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, const int lane, const bool live,
                                             const PT (&cur)[kRowBlocks][4], const PT (&gv)[kRowBlocks][4]) {
   using BT = typename BPack<P>::BT;
@@ -343,11 +374,14 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
     if (b0 >= PP) continue;
     PT z[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
     double sgd[4], invs[4], mu4[4], yt4[4], s4[4];
-    load4(a.sigma, true, b0, p, sgd);
-    load4(a.cc.inv_s, true, b0, PP, invs);
-    load4(a.cc.mu, true, b0, PP, mu4);
-    load4(a.cc.ytil, true, b0, PP, yt4);
-    load4(a.cc.s, true, b0, PP, s4);
+    // sigma: a block at or past p (only in padded markers) is never used, so with whole
+    // blocks the last one is read in its place
+    if constexpr (VR) vload4(a.sigma, b0 < p ? b0 : p - 4, sgd);
+    else load4(a.sigma, true, b0, p, sgd);
+    load4in<true>(a.cc.inv_s, true, b0, PP, invs);   // PP is a multiple of 32 and b0 < PP
+    load4in<true>(a.cc.mu, true, b0, PP, mu4);
+    load4in<true>(a.cc.ytil, true, b0, PP, yt4);
+    load4in<true>(a.cc.s, true, b0, PP, s4);
     const bool act = live && b0 < p;
     if (act)
       block_normals(philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(b0 >> 2), a.sweep,
@@ -358,7 +392,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int j = b0 + k;
-      if (act && j < p) {
+      if (act && (VR || j < p)) {   // VR: the whole block is in the row
         const PT sg = static_cast<PT>(sgd[k]);
         const PT c = cur[kb][k];
         if constexpr (MALA) {
@@ -379,14 +413,14 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
         }
       }
     }
-    if (act) store4(prop, vrow, b0, p, nv);
+    if (act) store4in<VR>(prop, vrow, b0, p, nv);
     // B operand of the proposal (zero in padded markers and padded particles)
     if (f8) {
       if constexpr (F8OK) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int j = b0 + k;
-          bv[kb][k] = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] * kLog2e : 0.0;
+          bv[kb][k] = (act && (VR || j < p)) ? static_cast<double>(nv[k]) * invs[k] * kLog2e : 0.0;
           mu8[kb][k] = mu4[k];
           yts8[kb][k] = yt4[k] * s4[k];
         }
@@ -396,7 +430,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int j = b0 + k;
-        const double bj = (act && j < p) ? static_cast<double>(nv[k]) * invs[k] : 0.0;
+        const double bj = (act && (VR || j < p)) ? static_cast<double>(nv[k]) * invs[k] : 0.0;
         double used;
         BPack<P>::put(bj, hb, lb, k, used);
         m += mu4[k] * used;
@@ -446,7 +480,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
 }
 
 // Load a particle row into the register layout above (zero outside the row).
-template <int LP, typename PT>
+template <int LP, bool VR, typename PT>
 __device__ __forceinline__ void load_row(const PT *row, const int lane, const int p, PT (&v)[kRowBlocks][4]) {
   const bool vrow = (p & 3) == 0;
 #pragma unroll
@@ -454,22 +488,22 @@ __device__ __forceinline__ void load_row(const PT *row, const int lane, const in
     const int b0 = lane * 4 + 4 * LP * kb;
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[kb][k] = PT(0);
-    if (b0 < p) load4(row, vrow, b0, p, v[kb]);
+    if (b0 < p) load4in<VR>(row, vrow, b0, p, v[kb]);
   }
 }
 
-template <int LP, typename PT>
+template <int LP, bool VR, typename PT>
 __device__ __forceinline__ void store_row(PT *row, const int lane, const int p, const PT (&v)[kRowBlocks][4]) {
   const bool vrow = (p & 3) == 0;
 #pragma unroll
   for (int kb = 0; kb < kRowBlocks; ++kb) {
     const int b0 = lane * 4 + 4 * LP * kb;
-    if (b0 < p) store4(row, vrow, b0, p, v[kb]);
+    if (b0 < p) store4in<VR>(row, vrow, b0, p, v[kb]);
   }
 }
 
 // One proposal sweep over all (padded) particle rows; LP lanes per particle.
-template <Prec P, typename PT, bool MALA, int LP, bool F8>
+template <Prec P, typename PT, bool MALA, int LP, bool F8, bool VR>
 __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
   const int lane = threadIdx.x & (LP - 1);
   const int i = static_cast<int>((blockIdx.x * blockDim.x + threadIdx.x) / LP);
@@ -477,10 +511,10 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
   const bool live = i < a.M;
   PT cur[kRowBlocks][4], gv[kRowBlocks][4];
   const int p = live ? a.p : 0;   // padded particles: all-zero rows
-  load_row<LP>(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
-  if constexpr (MALA) load_row<LP>(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
-  else load_row<LP>(static_cast<const PT *>(nullptr), lane, 0, gv);
-  propose_row<P, PT, MALA, LP, F8>(a, i, lane, live, cur, gv);
+  load_row<LP, VR>(reinterpret_cast<const PT *>(a.beta) + (size_t)i * a.p, lane, p, cur);
+  if constexpr (MALA) load_row<LP, VR>(reinterpret_cast<const PT *>(a.gl) + (size_t)i * a.p, lane, p, gv);
+  else load_row<LP, VR>(static_cast<const PT *>(nullptr), lane, 0, gv);
+  propose_row<P, PT, MALA, LP, F8, VR>(a, i, lane, live, cur, gv);
 }
 
 // Metropolis-Hastings decision for every particle; accepted rows are copied into the state.
@@ -493,7 +527,7 @@ __global__ __launch_bounds__(256) void propose_kernel(ProposeArgs a) {
 // sweeps.  The current gradient row is read with the other rows at the start, for every
 // particle (a rejected row needs it for its next proposal), so that no row load waits on
 // the decision.
-template <Prec P, typename PT, bool MALA, int SPL, bool NEXT, int LP, bool F8>
+template <Prec P, typename PT, bool MALA, int SPL, bool NEXT, int LP, bool F8, bool VR>
 __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs na) {
   constexpr bool PARTS = SPL > 0;
   const int lane = threadIdx.x & (LP - 1);
@@ -505,9 +539,9 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
   const Prior pr = a.prior;
   PT nv[kRowBlocks][4], cur[kRowBlocks][4], gnew[kRowBlocks][4];
   PT gold[(MALA && NEXT) ? kRowBlocks : 1][4];
-  load_row<LP>(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
-  load_row<LP>(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
-  if constexpr (MALA && NEXT) load_row<LP>(const_cast<const PT *>(gl), lane, p, gold);
+  load_row<LP, VR>(reinterpret_cast<const PT *>(a.prop) + (size_t)i * p, lane, p, nv);
+  load_row<LP, VR>(const_cast<const PT *>(beta), lane, MALA || NEXT ? p : 0, cur);
+  if constexpr (MALA && NEXT) load_row<LP, VR>(const_cast<const PT *>(gl), lane, p, gold);
   double llp;
   if constexpr (PARTS) {
     double spl = 0.0;
@@ -530,22 +564,22 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
 #pragma unroll
         for (int s = 0; s < SPL; ++s) {   // rows are PP long, PP a multiple of 32: aligned blocks
           PT t4[4];
-          load4(gp + (s * a.Mp + i) * PP, true, b0, PP, t4);
+          load4in<true>(gp + (s * a.Mp + i) * PP, true, b0, PP, t4);   // b0 < p <= PP
 #pragma unroll
           for (int k = 0; k < 4; ++k) acc[k] += static_cast<double>(t4[k]);
         }
         double yt4[4], mu4[4], is4[4];
-        load4(a.ytil, true, b0, PP, yt4);
-        load4(a.mu, true, b0, PP, mu4);
-        load4(a.inv_s, true, b0, PP, is4);
+        load4in<true>(a.ytil, true, b0, PP, yt4);
+        load4in<true>(a.mu, true, b0, PP, mu4);
+        load4in<true>(a.inv_s, true, b0, PP, is4);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
-          if (b0 + k < p) gnew[kb][k] = static_cast<PT>(yt4[k] - (acc[k] - mu4[k] * rho) * is4[k]);
+          if (VR || b0 + k < p) gnew[kb][k] = static_cast<PT>(yt4[k] - (acc[k] - mu4[k] * rho) * is4[k]);
       }
     }
   } else {
     llp = a.ll_prop[i];
-    if constexpr (MALA) load_row<LP>(reinterpret_cast<const PT *>(a.gl_prop) + (size_t)i * p, lane, p, gnew);
+    if constexpr (MALA) load_row<LP, VR>(reinterpret_cast<const PT *>(a.gl_prop) + (size_t)i * p, lane, p, gnew);
   }
   double lqr = 0.0;
   if constexpr (MALA) {
@@ -557,10 +591,10 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
       const int b0 = lane * 4 + 4 * LP * kb;
       if (b0 >= p) continue;
       double sgd[4];
-      load4(a.sigma, true, b0, p, sgd);
+      load4in<VR>(a.sigma, true, b0, p, sgd);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (b0 + k < p) {
+        if (VR || b0 + k < p) {
           const PT sg = static_cast<PT>(sgd[k]);
           const PT g = gnew[kb][k] + gt_grad_t<PT>(nv[kb][k], a1, ac, pr.inf, inv_c);
           const PT meanr = nv[kb][k] + PT(0.5) * step * sg * sg * g;
@@ -578,8 +612,8 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
   const double u = (static_cast<double>(w.x) + 0.5) * 0x1p-32;
   const bool acc = log(u) < log_alpha;   // false for NaN; the same in every lane of the group
   if (acc) {
-    store_row<LP>(beta, lane, p, nv);
-    if constexpr (MALA) store_row<LP>(gl, lane, p, gnew);
+    store_row<LP, VR>(beta, lane, p, nv);
+    if constexpr (MALA) store_row<LP, VR>(gl, lane, p, gnew);
     if (lane == 0) a.ll[i] = llp;
   }
   if (lane == 0) a.acc_cnt[i] = cnt + (acc ? 1 : 0);
@@ -593,7 +627,7 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
         if constexpr (MALA) gv[kb][k] = acc ? gnew[kb][k] : gold[kb][k];
         else gv[kb][k] = PT(0);
       }
-    propose_row<P, PT, MALA, LP, F8>(na, i, lane, true, nc, gv);
+    propose_row<P, PT, MALA, LP, F8, VR>(na, i, lane, true, nc, gv);
   }
 }
 
@@ -1217,10 +1251,16 @@ static inline int row_lanes(int PP) { return PP <= 256 ? 32 : 64; }
 
 template <Prec P, typename PT, bool MALA, bool F8 = false>
 static void launch_propose_t(const ProposeArgs &a, hipStream_t st) {
-  if (row_lanes(a.PP) == 32)
-    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32, F8>), dim3(grid_rows(a.M_pad, 8)), dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64, F8>), dim3(grid_rows(a.M_pad, 4)), dim3(256), 0, st, a);
+  const bool vr = (a.p & 3) == 0;   // whole 4-marker blocks in every particle row
+  if (row_lanes(a.PP) == 32) {
+    const dim3 grid(grid_rows(a.M_pad, 8));
+    if (vr) hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32, F8, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 32, F8, false>), grid, dim3(256), 0, st, a);
+  } else {
+    const dim3 grid(grid_rows(a.M_pad, 4));
+    if (vr) hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64, F8, true>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((propose_kernel<P, PT, MALA, 64, F8, false>), grid, dim3(256), 0, st, a);
+  }
 }
 
 void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) {
@@ -1237,15 +1277,21 @@ void launch_propose(Prec prec, bool mala, const ProposeArgs &a, hipStream_t st) 
   }
 }
 
-template <Prec P, typename PT, bool MALA, bool NEXT, int LP, bool F8>
-static void launch_accept_lp(int S, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
+template <Prec P, typename PT, bool MALA, bool NEXT, int LP, bool F8, bool VR>
+static void launch_accept_vr(int S, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
   const int grid = grid_rows(a.M, 256 / LP);
   switch (S) {
-    case 1: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 0, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
-    case 2: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 2, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
-    case 4: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 4, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
-    case 8: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 8, NEXT, LP, F8>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 1: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 0, NEXT, LP, F8, VR>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 2: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 2, NEXT, LP, F8, VR>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 4: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 4, NEXT, LP, F8, VR>), dim3(grid), dim3(256), 0, st, a, na); break;
+    case 8: hipLaunchKernelGGL((accept_kernel<P, PT, MALA, 8, NEXT, LP, F8, VR>), dim3(grid), dim3(256), 0, st, a, na); break;
   }
+}
+
+template <Prec P, typename PT, bool MALA, bool NEXT, int LP, bool F8>
+static void launch_accept_lp(int S, const AcceptArgs &a, const ProposeArgs &na, hipStream_t st) {
+  if ((a.p & 3) == 0) launch_accept_vr<P, PT, MALA, NEXT, LP, F8, true>(S, a, na, st);   // whole blocks
+  else launch_accept_vr<P, PT, MALA, NEXT, LP, F8, false>(S, a, na, st);
 }
 
 // S: the number of partial sums to combine (1: the contraction wrote whole results).
