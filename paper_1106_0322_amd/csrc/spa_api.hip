@@ -109,6 +109,7 @@ struct spa_smc {
   int *acc = nullptr, *anc = nullptr;
   OpScratch op;                  // operand of the sampler's own sweeps
   double *sigma = nullptr, *mean_path = nullptr, *var_path = nullptr, *part = nullptr;
+  void *mc = nullptr;            // per-marker move constants of the current step size (4 x PP)
   double *cdf = nullptr, *scal = nullptr;
   size_t cdf_cap = 0;
   double *rw_part = nullptr;     // workgroup partials of the reweighting pass
@@ -494,7 +495,7 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   pa.lp_cur = h->lpc;
   pa.lp_prop = h->lpp;
   pa.lqf = h->lqf;
-  pa.sigma = h->sigma;
+  pa.mc = h->mc;
   pa.cc.mu = h->mu;
   pa.cc.s = h->s;
   pa.cc.inv_s = h->inv_s;
@@ -523,11 +524,14 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
     pa.yb = h->f8_yb;
   }
   if (!have_prop) {
+    // the step size and the preconditioner hold for this sweep and the ones chained to it
+    launch_move_consts(h->f64, h->sigma, h->p, h->PP, h->step, pa.sqrt_step, h->mc, h->acc, h->N, h->stream);
     tbeg(h, SPA_T_PROPOSE);
     launch_propose(h->prec, mala, pa, h->stream);
     tend(h);
   }
   AcceptArgs aa{};
+  aa.PP = h->PP;   // row length of the move constants (and of the split adjoints below)
   if (h->f8_terms) {   // random-walk moves on the FP8 MFMA: the proposal is packed into terms
     Fp8xArgs fa;
     spa_status st = fp8x_contract(h, h->prop, h->N, 0, h->f8_terms, h->llp, false, &fa, false);
@@ -564,7 +568,7 @@ spa_status sweep(spa_smc *h, int t, int s, double lam, bool have_prop = false, b
   aa.lp_cur = h->lpc;
   aa.lp_prop = h->lpp;
   aa.lqf = h->lqf;
-  aa.sigma = h->sigma;
+  aa.mc = h->mc;
   aa.acc_cnt = h->acc;
   aa.prior = pr;
   aa.step = h->step;
@@ -959,6 +963,7 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   SPA_AL(h->acc, 4 * (size_t)h->Npad);
   SPA_AL(h->anc, 4 * (size_t)h->Npad);
   SPA_AL(h->sigma, 8 * kMaxPP);
+  SPA_AL(h->mc, 8 * 4 * kMaxPP);
   SPA_AL(h->mean_path, 8 * (size_t)h->T * p);
   SPA_AL(h->var_path, 8 * (size_t)h->T * p);
   SPA_AL(h->part, 8 * 3 * (size_t)moments_chunks(h->N) * p);
@@ -1021,8 +1026,7 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
       launch_moments(h->f64, h->beta, h->logw, nullptr, h->N, p, h->part, nullptr, nullptr, h->sigma, kSigmaFloor,
                      h->stream);
     }
-    launch_zero_int(h->acc, h->N, h->stream);
-    if ((st = sweep(h, 0, s, h->lambda[0])) != SPA_OK) return fail(st);
+    if ((st = sweep(h, 0, s, h->lambda[0])) != SPA_OK) return fail(st);   // zeroes the accept counters
     long long cnt = 0;
     if ((st = read_count(h, &cnt)) != SPA_OK) return fail(st);
     adapt_step(h, static_cast<double>(cnt) / h->N);
@@ -1116,11 +1120,11 @@ extern "C" spa_status spa_smc_step(spa_smc *h, spa_smc_stats *out) {
   launch_moments(h->f64, h->beta, h->logw, resampled ? nullptr : h->scal + 1, h->N, h->p, h->part, nullptr, nullptr,
                  h->sigma, kSigmaFloor, h->stream);
   tend(h);
-  launch_zero_int(h->acc, h->N, h->stream);
   const double step_used = h->step;
   if (h->move == SPA_MOVE_SINGLE) {
+    launch_zero_int(h->acc, h->N, h->stream);
     if (h->sweeps > 0 && (st = single_site_cycles(h, t_new, h->sweeps, lam_new)) != SPA_OK) return st;
-  } else {
+  } else {   // the first sweep's move-constants launch zeroes the accept counters
     for (int s = 0; s < h->sweeps; ++s)
       if ((st = sweep(h, t_new, s, lam_new, s > 0, s + 1 < h->sweeps)) != SPA_OK) return st;
   }

@@ -269,6 +269,13 @@ __device__ __forceinline__ void store4in(T *dst, bool vec, int j0, int lim, cons
   else store4(dst, vec, j0, lim, v);
 }
 
+// x / v for a per-marker variance v stored by the move-constants kernel: FP32 stores the
+// hardware reciprocal of v (so this is div_t(x, v)), FP64 stores v.
+__device__ __forceinline__ float div_pre(float x, float stored) { return x * stored; }
+__device__ __forceinline__ double div_pre(double x, double stored) { return x / stored; }
+__device__ __forceinline__ float pre_div(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ double pre_div(double v) { return v; }
+
 // Particle rows in registers: LP lanes per particle (64, or 32 for rows of at most 256
 // markers, two particles per wave); sub-lane l holds markers 4l..4l+3 and
 // 4LP+4l..4LP+4l+3 (one Philox block of four normals each), which covers p <= 8 LP - 1.
@@ -355,7 +362,7 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
   const PT inv_ac = pr.inf ? PT(0) : static_cast<PT>(1.0 / (pr.a * pr.lam));
   const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
   const PT inv_c = static_cast<PT>(1.0 / pr.lam);
-  const PT step = static_cast<PT>(a.step), sqrt_step = static_cast<PT>(a.sqrt_step);
+  const PT *mc = static_cast<const PT *>(a.mc);
   double m = 0.0, ybv = 0.0, lpc = 0.0, lpp = 0.0, lqf = 0.0;
   // FP8 multi-term operand (random-walk rows only): the scaled coefficients are kept until
   // the row is complete, then split into terms
@@ -373,11 +380,17 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
     const int b0 = lane * 4 + 4 * LP * kb;
     if (b0 >= PP) continue;
     PT z[4] = {0, 0, 0, 0}, nv[4] = {0, 0, 0, 0};
-    double sgd[4], invs[4], mu4[4], yt4[4], s4[4];
-    // sigma: a block at or past p (only in padded markers) is never used, so with whole
-    // blocks the last one is read in its place
-    if constexpr (VR) vload4(a.sigma, b0 < p ? b0 : p - 4, sgd);
-    else load4(a.sigma, true, b0, p, sgd);
+    // per-marker constants (PP-long rows): MALA drift, variance and noise scale, or the
+    // random-walk scale
+    PT hs[4], dv[4], ss[4];
+    if constexpr (MALA) {
+      load4in<true>(mc, true, b0, PP, hs);
+      load4in<true>(mc + PP, true, b0, PP, dv);
+      load4in<true>(mc + 2 * PP, true, b0, PP, ss);
+    } else {
+      load4in<true>(mc + 3 * PP, true, b0, PP, ss);
+    }
+    double invs[4], mu4[4], yt4[4], s4[4];
     load4in<true>(a.cc.inv_s, true, b0, PP, invs);   // PP is a multiple of 32 and b0 < PP
     load4in<true>(a.cc.mu, true, b0, PP, mu4);
     load4in<true>(a.cc.ytil, true, b0, PP, yt4);
@@ -393,16 +406,15 @@ __device__ __forceinline__ void propose_row(const ProposeArgs &a, const int i, c
     for (int k = 0; k < 4; ++k) {
       const int j = b0 + k;
       if (act && (VR || j < p)) {   // VR: the whole block is in the row
-        const PT sg = static_cast<PT>(sgd[k]);
         const PT c = cur[kb][k];
         if constexpr (MALA) {
           const PT g = gv[kb][k] + gt_grad_t<PT>(c, a1, ac, pr.inf, inv_c);
-          const PT meanf = c + PT(0.5) * step * sg * sg * g;
-          nv[k] = meanf + sqrt_step * sg * z[k];
+          const PT meanf = c + hs[k] * g;
+          nv[k] = meanf + ss[k] * z[k];
           const PT d = nv[k] - meanf;
-          q += div_t(d * d, PT(2) * step * sg * sg);
+          q += div_pre(d * d, dv[k]);
         } else {
-          nv[k] = c + step * sg * z[k];
+          nv[k] = c + ss[k] * z[k];
         }
         if (pr.inf) {
           lc += fabs(c);
@@ -584,22 +596,23 @@ __global__ __launch_bounds__(256) void accept_kernel(AcceptArgs a, ProposeArgs n
   double lqr = 0.0;
   if constexpr (MALA) {
     const PT a1 = static_cast<PT>(pr.a + 1.0), ac = static_cast<PT>(pr.a * pr.lam);
-    const PT inv_c = static_cast<PT>(1.0 / pr.lam), step = static_cast<PT>(a.step);
+    const PT inv_c = static_cast<PT>(1.0 / pr.lam);
+    const PT *mc = static_cast<const PT *>(a.mc);
     PT q = PT(0);
 #pragma unroll
     for (int kb = 0; kb < kRowBlocks; ++kb) {
       const int b0 = lane * 4 + 4 * LP * kb;
       if (b0 >= p) continue;
-      double sgd[4];
-      load4in<VR>(a.sigma, true, b0, p, sgd);
+      PT hs[4], dv[4];
+      load4in<true>(mc, true, b0, a.PP, hs);   // b0 < p <= PP
+      load4in<true>(mc + a.PP, true, b0, a.PP, dv);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (VR || b0 + k < p) {
-          const PT sg = static_cast<PT>(sgd[k]);
           const PT g = gnew[kb][k] + gt_grad_t<PT>(nv[kb][k], a1, ac, pr.inf, inv_c);
-          const PT meanr = nv[kb][k] + PT(0.5) * step * sg * sg * g;
+          const PT meanr = nv[kb][k] + hs[k] * g;
           const PT d = cur[kb][k] - meanr;
-          q += div_t(d * d, PT(2) * step * sg * sg);
+          q += div_pre(d * d, dv[k]);
         }
       }
     }
@@ -1402,6 +1415,34 @@ void launch_count(const int *cnt, int M, const double *ll, long long *out, hipSt
 void launch_fill(double *x, int n, double v, hipStream_t st) {
   hipLaunchKernelGGL(fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n, v);
 }
+template <typename PT>
+__global__ void move_consts_kernel(const double *__restrict__ sigma, int p, int PP, double step, double sqrt_step,
+                                   PT *__restrict__ mc, int *__restrict__ acc, int N) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < N) acc[t] = 0;
+  if (t < PP) {
+    // the products the move kernels formed per coefficient, in the same order
+    const PT st = static_cast<PT>(step), sst = static_cast<PT>(sqrt_step);
+    const PT sg = t < p ? static_cast<PT>(sigma[t]) : PT(0);
+    mc[t] = PT(0.5) * st * sg * sg;
+    mc[PP + t] = pre_div(PT(2) * st * sg * sg);
+    mc[2 * PP + t] = sst * sg;
+    mc[3 * PP + t] = st * sg;
+  }
+}
+
+void launch_move_consts(bool f64, const double *sigma, int p, int PP, double step, double sqrt_step, void *mc,
+                        int *acc, int N, hipStream_t st) {
+  const int n = std::max(N, PP);
+  const dim3 grid((n + 255) / 256);
+  if (f64)
+    hipLaunchKernelGGL(move_consts_kernel<double>, grid, dim3(256), 0, st, sigma, p, PP, step, sqrt_step,
+                       static_cast<double *>(mc), acc, N);
+  else
+    hipLaunchKernelGGL(move_consts_kernel<float>, grid, dim3(256), 0, st, sigma, p, PP, step, sqrt_step,
+                       static_cast<float *>(mc), acc, N);
+}
+
 void launch_zero_int(int *x, int n, hipStream_t st) {
   hipLaunchKernelGGL(zero_int_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, n);
 }

@@ -20,7 +20,7 @@ struct ProposeArgs {
   void *Bhi, *Blo;       // M_pad x PP B operand of the proposal
   double *moff, *yb;     // M_pad
   double *lp_cur, *lp_prop, *lqf;   // M
-  const double *sigma;   // p preconditioner
+  const void *mc;        // 4 x PP per-marker move constants (launch_move_consts), PT
   struct {
     const double *mu, *s, *inv_s, *ytil;   // PP-padded column constants
   } cc;
@@ -50,7 +50,7 @@ struct AcceptArgs {
   int S, PP;
   size_t Mp;
   const double *yb, *mu, *inv_s, *ytil;
-  const double *sigma;
+  const void *mc;                   // 4 x PP per-marker move constants, PT
   int *acc_cnt;
   Prior prior;
   double step;
@@ -123,6 +123,13 @@ void launch_moments(bool f64, const void *beta, double *logw, const double *shif
 void launch_count(const int *cnt, int M, const double *ll, long long *out, hipStream_t st);
 void launch_fill(double *x, int n, double v, hipStream_t st);
 void launch_zero_int(int *x, int n, hipStream_t st);
+// Per-marker constants of the proposal and decision kernels for one step size and
+// preconditioner, in the particle precision (double when f64, else float), written to mc
+// (4 x PP): (0.5 step) sigma sigma; the MALA variance 2 step sigma sigma (in FP32 its
+// hardware reciprocal); sqrt(step) sigma; step sigma (sigma = 0 in padded markers).  The
+// kernel also zeroes the N acceptance counters acc.  sqrt_step is sqrt(step) in FP64.
+void launch_move_consts(bool f64, const double *sigma, int p, int PP, double step, double sqrt_step, void *mc,
+                        int *acc, int N, hipStream_t st);
 void launch_convert(bool src_f64, const void *src, void *dst, size_t n, hipStream_t st);
 void launch_add_prior(bool beta_f64, bool g_f64, const void *beta, int M, int p, const Prior &pr, void *g,
                       const double *ll, double *logpost, hipStream_t st);
