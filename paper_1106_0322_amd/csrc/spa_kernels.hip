@@ -1421,7 +1421,7 @@ __global__ void move_consts_kernel(const double *__restrict__ sigma, int p, int 
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < N) acc[t] = 0;
   if (t < PP) {
-    // the products the move kernels formed per coefficient, in the same order
+    // each product in the order the proposal and decision formulas take it per coefficient
     const PT st = static_cast<PT>(step), sst = static_cast<PT>(sqrt_step);
     const PT sg = t < p ? static_cast<PT>(sigma[t]) : PT(0);
     mc[t] = PT(0.5) * st * sg * sg;
