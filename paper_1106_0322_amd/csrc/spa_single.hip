@@ -12,10 +12,11 @@
 // The FP32 instance uses softplus(z) = z/2 + |z|/2 + log(1 + e^{-|z|}): with d_k = delta x_k
 // the likelihood difference of a move is
 //   delta c_j + (1/2) sum_k (|eta_k| - |eta_k + d_k|) + log(prod_k (1 + e^{-|eta_k|}) / prod_k (1 + e^{-|eta_k + d_k|})),
-// c_j = sum_k (y_k - 1/2) x_kj one number per column, sum_k |eta_k| kept per lane (replaced
-// on acceptance), the two products accumulated with FMAs and divided once per lane; eta is
-// kept in log2 units so that e^{-|eta|} is one exp2.  Per individual and move: one FMA for
-// the new eta, one exponential, two FMAs for the products and one add.  The particle's coefficients are held by lane j mod 64 and
+// c_j = sum_k (y_k - 1/2) x_kj one number per column; sum_k |eta_k| and the product over the
+// current state are kept per lane (replaced on acceptance by the proposal's), the proposal's
+// product accumulated with FMAs and the two divided once per lane; eta is kept in log2
+// units so that e^{-|eta|} is one exp2.  Per individual and move: one FMA for the new eta,
+// one exponential, one FMA for the product and one add.  The particle's coefficients are held by lane j mod 64 and
 // broadcast with readlane; the cycle's normals and uniforms are drawn up front, one
 // Philox block per coordinate, by the lane holding that coordinate.
 #include <hip/hip_runtime.h>
@@ -136,6 +137,11 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
       em[r] = __builtin_amdgcn_exp2f(-fabsf(eta[r]));
       sa += fabsf(eta[r]);
     }
+    // this lane's product of (1 + e^-|eta|), formed in the same order as a proposal's (so an
+    // accepted proposal's product is exactly the product of the new state)
+    float pm = 1.0f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) pm = fmaf(pm, em[r], pm);
     for (int c = 0; c < a.cycles; ++c) {
       const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
       float zv[kMaxCoordBlocks];
@@ -162,18 +168,17 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
           const float dl = delta * kL2e;
           const PT *col = xs + (size_t)j * n_pad;
           float e1[R], en[R];
-          float num = 1.0f, den = 1.0f, sn = 0.0f;
+          float den = 1.0f, sn = 0.0f;
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int k = lane + 64 * r;
             const float x = k < n_pad ? col[k] : 0.0f;
             e1[r] = fmaf(dl, x, eta[r]);
             en[r] = __builtin_amdgcn_exp2f(-fabsf(e1[r]));
-            num = fmaf(num, em[r], num);
             den = fmaf(den, en[r], den);
             sn += fabsf(e1[r]);
           }
-          const float part = kLn2 * (0.5f * (sa - sn) + __builtin_amdgcn_logf(num * __builtin_amdgcn_rcpf(den)));
+          const float part = kLn2 * (0.5f * (sa - sn) + __builtin_amdgcn_logf(pm * __builtin_amdgcn_rcpf(den)));
           const float dll = wave_total_f32(part) + delta * a.cs[j];
           const float bj = bcast(bv[m], jl);
           const float bn = bj + delta;
@@ -186,6 +191,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
               em[r] = en[r];
             }
             sa = sn;
+            pm = den;
             if (lane == jl) bv[m] = bn;
             ++cnt;
           }
