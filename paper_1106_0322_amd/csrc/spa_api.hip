@@ -154,6 +154,7 @@ struct spa_smc {
   double *map_starts = nullptr, *map_modes = nullptr, *map_mlp = nullptr;
   // single-coordinate kernel operands (standardised genotype columns, labels)
   void *xs_ss = nullptr, *yv_ss = nullptr;
+  int ss_rows = 0;          // padded individuals of xs_ss / yv_ss (single_site_rows(n))
   float *cs_ss = nullptr;   // FP32: column coefficients sum_k (y_k - 1/2) xs_jk
   // sparsity-path summaries (per scale, and the c-marginal mixture)
   SqLevels sq_lv{};
@@ -630,7 +631,7 @@ spa_status single_site_cycles(spa_smc *h, int t, int cycles, double lam) {
   a.step = h->step;
   a.M = h->N;
   a.n = h->n;
-  a.n_pad = h->n_pad;
+  a.n_pad = h->ss_rows;
   a.p = h->p;
   a.cycles = cycles;
   a.cycle0 = 0;
@@ -994,18 +995,19 @@ extern "C" spa_status spa_smc_init(const spa_smc_config *cfg, const uint8_t *X_h
   launch_col_stats(h->dX, h->dy, n, p, h->mu, h->s, h->inv_s, h->ytil, h->dbad, h->stream);
   if (!h->f8_terms && (st = ensure_xpack(h, h->prec)) != SPA_OK) return fail(st);
   if (h->move == SPA_MOVE_SINGLE) {
-    if ((st = dalloc(h, &h->xs_ss, h->psz * (size_t)p * h->n_pad)) != SPA_OK) return fail(st);
-    if ((st = dalloc(h, &h->yv_ss, h->psz * (size_t)h->n_pad)) != SPA_OK) return fail(st);
-    he = launch_std_cols(h->f64, h->dX, n, p, h->n_pad, h->mu, h->s, h->xs_ss, h->stream);
+    h->ss_rows = single_site_rows(n);   // n <= single_site_max_n() was checked above
+    if ((st = dalloc(h, &h->xs_ss, h->psz * (size_t)p * h->ss_rows)) != SPA_OK) return fail(st);
+    if ((st = dalloc(h, &h->yv_ss, h->psz * (size_t)h->ss_rows)) != SPA_OK) return fail(st);
+    he = launch_std_cols(h->f64, h->dX, n, p, h->ss_rows, h->mu, h->s, h->xs_ss, h->stream);
     if (he != hipSuccess) {
       hip_fail(h, he, "std_cols");
       return fail(SPA_ERR_HIP);
     }
-    launch_labels(h->dy, n, h->n_pad, h->f64, h->yv_ss, h->stream);
+    launch_labels(h->dy, n, h->ss_rows, h->f64, h->yv_ss, h->stream);
     if (!h->f64) {
       if ((st = dalloc(h, &h->cs_ss, sizeof(float) * (size_t)p)) != SPA_OK) return fail(st);
       he = launch_lin_cols(static_cast<const float *>(h->xs_ss), static_cast<const float *>(h->yv_ss), n, p,
-                           h->n_pad, h->cs_ss, h->stream);
+                           h->ss_rows, h->cs_ss, h->stream);
       if (he != hipSuccess) {
         hip_fail(h, he, "lin_cols");
         return fail(SPA_ERR_HIP);

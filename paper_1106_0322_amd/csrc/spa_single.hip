@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
   const int i = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (i >= a.M) return;
   const int n = a.n, n_pad = a.n_pad, p = a.p;
-  const PT *xs = reinterpret_cast<const PT *>(a.xs);   // p x n_pad, zero padded
+  const PT *xs = reinterpret_cast<const PT *>(a.xs);   // p x n_pad, zero padded; n_pad = 64 R
   const PT *yv = reinterpret_cast<const PT *>(a.yv);
   PT *beta = reinterpret_cast<PT *>(a.beta) + (size_t)i * p;
   const Prior pr = a.prior;
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
   for (int r = 0; r < R; ++r) {
     eta[r] = PT(0);
     const int k = lane + 64 * r;
-    yk[r] = k < n_pad ? yv[k] : PT(0);
+    yk[r] = yv[k];
   }
 #pragma unroll
   for (int m = 0; m < kMaxCoordBlocks; ++m) {
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int k = lane + 64 * r;
-        if (k < n_pad) eta[r] += bj * col[k];
+        eta[r] += bj * col[k];
       }
     }
   }
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const int k = lane + 64 * r;
-            const float x = k < n_pad ? col[k] : 0.0f;
+            const float x = col[k];
             e1[r] = fmaf(dl, x, eta[r]);
             en[r] = __builtin_amdgcn_exp2f(-fabsf(e1[r]));
             den = fmaf(den, en[r], den);
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int k = lane + 64 * r;
-          const PT x = k < n_pad ? col[k] : PT(0);
+          const PT x = col[k];
           d[r] = delta * x;
           const PT e1 = eta[r] + d[r];
           en[r] = exp_neg(fabs(e1));
@@ -314,18 +314,25 @@ static void launch_r(const SingleSiteArgs &a, hipStream_t st) {
 
 template <typename PT>
 static hipError_t launch_t(const SingleSiteArgs &a, hipStream_t st) {
-  const int R = (a.n_pad + 63) / 64;
-  if (R <= 4) launch_r<PT, 4>(a, st);
-  else if (R <= 8) launch_r<PT, 8>(a, st);
-  else if (R <= 16) launch_r<PT, 16>(a, st);
-  else if (R <= 32) launch_r<PT, 32>(a, st);
-  else return hipErrorInvalidValue;
+  switch (a.n_pad) {   // the columns are padded to exactly 64 R individuals
+    case 64 * 4: launch_r<PT, 4>(a, st); break;
+    case 64 * 8: launch_r<PT, 8>(a, st); break;
+    case 64 * 16: launch_r<PT, 16>(a, st); break;
+    case 64 * 32: launch_r<PT, 32>(a, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
 int single_site_max_n() { return 64 * 32; }
+
+int single_site_rows(int n) {
+  for (int R = 4; R <= 32; R *= 2)
+    if (n <= 64 * R) return 64 * R;
+  return -1;
+}
 
 hipError_t launch_single_site(bool f64, const SingleSiteArgs &a, hipStream_t st) {
   if (a.p > 64 * kMaxCoordBlocks) return hipErrorInvalidValue;
