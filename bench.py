@@ -86,14 +86,14 @@ def copy_calibration():
 # multiply-add): 3 + 4 = 7 VALU lane-slots.  The chip's VALU lane-slot rate is
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (the 157.3 TFLOP/s FP32 vector peak counts an FMA
 # as two flops and packed FP32 as two lanes).  For comparison the FP32 kernel itself issues
-# 63 VALU + 13 transcendental instructions per coordinate update of 8 individuals per lane
+# 50 VALU + 10 transcendental instructions per coordinate update of 8 individuals per lane
 # on the path without acceptance (its ISA: the update loop minus the acceptance block; the
-# transcendentals are the 8 exponentials and a reciprocal and a logarithm each for the
-# likelihood ratio, the prior difference and the MH uniform; an accepted move adds 8
-# register moves), about 14.4 lane-slots per element update; the ratio of the two is its
-# overhead.
+# transcendentals are the 8 exponentials and the reciprocal and logarithm of the likelihood
+# ratio; the move, the prior difference and log u are formed once per coordinate and cycle
+# by the lane holding the coordinate; an accepted move adds 9 vector instructions), about
+# 11.3 lane-slots per element update; the ratio of the two is its overhead.
 SINGLE_SITE_ALG_SLOTS = 3 + 4 * 1
-SINGLE_SITE_SLOTS = (63 + 4 * 13) / 8.0
+SINGLE_SITE_SLOTS = (50 + 4 * 10) / 8.0
 VALU_LANE_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 
 

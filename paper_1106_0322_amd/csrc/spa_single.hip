@@ -144,19 +144,21 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
     for (int r = 0; r < R; ++r) pm = fmaf(pm, em[r], pm);
     for (int c = 0; c < a.cycles; ++c) {
       const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
-      float zv[kMaxCoordBlocks];
-      uint32_t uw[kMaxCoordBlocks];
+      // per coordinate, by the lane holding it: the move delta, log Gt(b + delta) - log Gt(b)
+      // and log u (a coordinate changes only at its own update, so these are the values its
+      // update needs)
+      float dz[kMaxCoordBlocks], dp[kMaxCoordBlocks], lu[kMaxCoordBlocks];
 #pragma unroll
       for (int m = 0; m < kMaxCoordBlocks; ++m) {
         const int j = lane + 64 * m;
-        zv[m] = 0.0f;
-        uw[m] = 0u;
+        dz[m] = dp[m] = lu[m] = 0.0f;
         if (64 * m < p && j < p) {
           const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j), cyc,
                                                    word3(a.t, kTagSingleSite)),
                                         a.k0, a.k1);
-          zv[m] = draw_normal(w, 0.0f);
-          uw[m] = w.z;
+          dz[m] = step * draw_normal(w, 0.0f);
+          dp[m] = prior_diff(bv[m] + dz[m], bv[m], pr);
+          lu[m] = log_uniform(w.z, 0.0f);
         }
       }
 #pragma unroll
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
         if (64 * m >= p) break;
         for (int jl = 0; jl < 64 && 64 * m + jl < p; ++jl) {
           const int j = 64 * m + jl;
-          const float delta = step * bcast(zv[m], jl);
+          const float delta = bcast(dz[m], jl);
           const float dl = delta * kL2e;
           const PT *col = xs + (size_t)j * n_pad;
           float e1[R], en[R];
@@ -180,19 +182,12 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
           }
           const float part = kLn2 * (0.5f * (sa - sn) + __builtin_amdgcn_logf(pm * __builtin_amdgcn_rcpf(den)));
           const float dll = wave_total_f32(part) + delta * a.cs[j];
-          const float bj = bcast(bv[m], jl);
-          const float bn = bj + delta;
-          const float dlp = prior_diff(bn, bj, pr);
-          const uint32_t w2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(uw[m]), jl));
-          if (log_uniform(w2, 0.0f) < dll + dlp) {   // uniform across the wave (lane-identical sums)
+          if (bcast(lu[m], jl) < dll + bcast(dp[m], jl)) {   // uniform across the wave (lane-identical sums)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-              eta[r] = e1[r];
-              em[r] = en[r];
-            }
+            for (int r = 0; r < R; ++r) eta[r] = e1[r];
             sa = sn;
             pm = den;
-            if (lane == jl) bv[m] = bn;
+            if (lane == jl) bv[m] += dz[m];
             ++cnt;
           }
         }
@@ -206,19 +201,19 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
 
   for (int c = 0; c < a.cycles; ++c) {
     const uint32_t cyc = static_cast<uint32_t>(a.cycle0 + c);
-    PT zv[kMaxCoordBlocks];
-    uint32_t uw[kMaxCoordBlocks];   // MH uniform u = (w2 + 1/2) 2^-32, kept as its word
+    // per coordinate, by the lane holding it: the move, the prior difference and log u
+    PT dz[kMaxCoordBlocks], dp[kMaxCoordBlocks], lu[kMaxCoordBlocks];
 #pragma unroll
     for (int m = 0; m < kMaxCoordBlocks; ++m) {
       const int j = lane + 64 * m;
-      zv[m] = PT(0);
-      uw[m] = 0u;
+      dz[m] = dp[m] = lu[m] = PT(0);
       if (64 * m < p && j < p) {
         const uint4 w = philox4x32_10(make_uint4(static_cast<uint32_t>(i), static_cast<uint32_t>(j), cyc,
                                                  word3(a.t, kTagSingleSite)),
                                       a.k0, a.k1);
-        zv[m] = draw_normal(w, PT(0));
-        uw[m] = w.z;
+        dz[m] = step * draw_normal(w, PT(0));
+        dp[m] = prior_diff(bv[m] + dz[m], bv[m], pr);
+        lu[m] = log_uniform(w.z, PT(0));
       }
     }
 #pragma unroll
@@ -226,7 +221,7 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
       if (64 * m >= p) break;
       for (int jl = 0; jl < 64 && 64 * m + jl < p; ++jl) {
         const int j = 64 * m + jl;
-        const PT delta = step * bcast(zv[m], jl);
+        const PT delta = bcast(dz[m], jl);
         const PT *col = xs + (size_t)j * n_pad;
         PT d[R], en[R];
         PT prod = PT(1), lin = PT(0);
@@ -242,17 +237,13 @@ __global__ __launch_bounds__(256) void single_site_kernel(SingleSiteArgs a) {
           lin += yk[r] * d[r] + (fmax(eta[r], PT(0)) - fmax(e1, PT(0)));
         }
         const PT dll = wave_sum_t(lin + log_t(prod));
-        const PT bj = bcast(bv[m], jl);
-        const PT bn = bj + delta;
-        const PT dlp = prior_diff(bn, bj, pr);
-        const uint32_t w2 = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(uw[m]), jl));
-        if (log_uniform(w2, PT(0)) < dll + dlp) {   // uniform across the wave (lane-identical sums)
+        if (bcast(lu[m], jl) < dll + bcast(dp[m], jl)) {   // uniform across the wave (lane-identical sums)
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             eta[r] += d[r];
             em[r] = en[r];
           }
-          if (lane == jl) bv[m] = bn;
+          if (lane == jl) bv[m] += dz[m];
           ++cnt;
         }
       }
